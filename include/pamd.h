@@ -1,0 +1,291 @@
+/*
+ * pamd.h -- C ABI of libpamd, the MI355X (gfx950) implementation of the
+ * discretized Brownian path action and its gradient.
+ *
+ * Method: Rosa-Raices, Zhang, Miller, "Path-accelerated molecular dynamics:
+ * parallel-in-time integration using path integrals", arXiv:1907.09529.
+ *
+ * A path is X = {x_0, ..., x_N} (Sec. II A, above Eq. 4): N time steps of
+ * length dt and N + 1 configurations ("slices").  For overdamped Langevin
+ * dynamics (Eq. 1) discretized by Euler-Maruyama (Eq. 2), each step has the
+ * Gaussian transition density of Eq. 3 and the path likelihood is
+ * prod_n K(x_{n+1} | x_n; dt) = exp(-S[X]) (Eq. 4).  This library evaluates,
+ * for all steps at once,
+ *
+ *     r_n = Delta_n - (dt / gamma) F(x_n),      Delta_n = x_{n+1} - x_n (minimum image),
+ *     s_n = |r_n|^2 / (4 D dt),                 S = sum_{n<N} s_n,
+ *
+ * with F = -V' (harmonic, or the cut-and-force-shifted Lennard-Jones pair
+ * potential of Eq. 16 under cubic periodic boundaries), and the gradient
+ *
+ *     g_m = dS/dx_m = c [ w_{m-1} r_{m-1} - w_m r_m + (dt/gamma) H(x_m) w_m r_m ],  c = 1/(2 D dt),
+ *
+ * (terms with an index outside 0..N-1 vanish; H is the potential-energy
+ * Hessian, applied as a Hessian-vector product and never formed; w_n are
+ * optional per-step weights, all 1 by default, giving the gradient of
+ * sum_n w_n s_n).  S excludes the normalisation of the N Gaussian densities;
+ * pamd_log_norm() returns it.
+ *
+ * Conventions for every entry point
+ *   - Memory layout: a path is float64, contiguous, slice-major with the
+ *     coordinates of one slice grouped by component:
+ *         x[(n * n_dim + c) * n_atoms + i],  n = 0..N, c = 0..n_dim-1.
+ *     Coordinates are unwrapped (no periodic folding is required or applied).
+ *   - Pointers named "device" must be device memory of the current HIP device
+ *     (e.g. torch tensors' data_ptr()); "host" pointers are host memory.
+ *     The caller owns all buffers.  The library never allocates device memory.
+ *   - Every call is asynchronous on `stream` (a hipStream_t; NULL = the null
+ *     stream).  Results are valid once the stream has reached them.
+ *   - Workspace: `ws` is caller-provided device memory of at least the size
+ *     reported by the matching *_workspace_size call, 256-byte aligned.  Its
+ *     contents need no initialisation and are not meaningful after a call.
+ *     Two calls that overlap in time must not share a workspace.
+ *   - Errors: 0 on success, a negative PAMD_E* code otherwise; then
+ *     pamd_last_error() returns a message (thread-local).  All arguments are
+ *     validated on the host before any device work is enqueued, so a failed
+ *     call has no device side effects.  Non-finite coordinates are not
+ *     checked: they propagate as IEEE NaN/Inf.
+ *   - Calls enqueue kernels only (no memset, no host synchronisation), so they
+ *     may be captured into a HIP graph (see pamd_graph_*).  pamd_autotune is
+ *     the exception: it synchronises and must not be captured.
+ */
+#ifndef PAMD_H
+#define PAMD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- error codes ---- */
+#define PAMD_OK 0
+#define PAMD_EINVAL (-1)          /* malformed argument (null pointer, bad size, bad value) */
+#define PAMD_EUNSUPPORTED (-2)    /* well-formed but outside what the library implements */
+#define PAMD_EWORKSPACE (-3)      /* ws_bytes smaller than required, or ws misaligned */
+#define PAMD_EHIP (-4)            /* a HIP runtime call failed (message has the HIP error) */
+
+/* ---- potential kinds (pamd_potential.kind) ---- */
+#define PAMD_HARMONIC 0           /* V = k/2 sum x^2 over all degrees of freedom (Sec. IV A) */
+#define PAMD_LJ 1                 /* cut-and-force-shifted LJ pair potential, Eq. 16 (Sec. IV B) */
+
+/* ---- force precision (pamd_path.precision) ---- */
+#define PAMD_FP64 0               /* all arithmetic in float64 */
+#define PAMD_FP32_FORCE 1         /* LJ pair functions and pair products in float32; displacements,
+                                     cutoff test, force and Hessian-vector sums, residuals, actions
+                                     and gradients in float64.  Harmonic paths ignore this. */
+
+/* ---- algorithm choice (pamd_tuning.algo) ---- */
+#define PAMD_ALGO_AUTO 0          /* fused */
+#define PAMD_ALGO_FUSED 1         /* one pass per time tile: neighbour list, force, residual,
+                                     action, Hessian-vector product and gradient on chip */
+#define PAMD_ALGO_PLAIN 2         /* unfused reference form: per-slice cell list, then separate
+                                     force, residual, Hessian-vector and gradient kernels with
+                                     every intermediate in device memory */
+
+/* Potential.  kind = PAMD_HARMONIC uses k; kind = PAMD_LJ uses eps, sigma,
+ * rc and box (Eq. 16 with epsilon = eps, sigma = sigma, r_c = rc; periodic
+ * cubic box of edge `box`, minimum-image convention, pair included when
+ * r^2 <= rc^2).  Requirements: LJ: eps, sigma > 0, 0 < rc <= box/2, n_dim = 3.
+ * Harmonic: box must be 0 (no periodic boundaries). */
+typedef struct pamd_potential {
+  int32_t kind;
+  int32_t reserved0;
+  double k;
+  double eps;
+  double sigma;
+  double rc;
+  double box;
+} pamd_potential;
+
+/* Path description (Eqs. 1-4).  n_steps = N >= 1 (the path holds N + 1
+ * slices), n_atoms >= 1 (at most 65535 for LJ), n_dim in {1, 3}, dt > 0,
+ * D > 0 (diffusion coefficient), gamma > 0 (friction; the Einstein relation
+ * of Eq. 1, D = 1/(beta gamma), is the caller's to apply). */
+typedef struct pamd_path {
+  int64_t n_steps;
+  int32_t n_atoms;
+  int32_t n_dim;
+  double dt;
+  double D;
+  double gamma;
+  int32_t precision;
+  int32_t reserved0;
+} pamd_path;
+
+/* Optional launch tuning; pass NULL (or a zeroed struct) for the library's
+ * choice (the autotune cache when an entry exists, else built-in defaults).
+ * Fields equal to 0 (skin <= 0) are chosen by the library.
+ *   block          threads per workgroup, multiple of 64 in [64, 1024]
+ *   tile           time steps per workgroup tile (fused)
+ *   skin           neighbour-list skin in length units (fused): a list built
+ *                  with radius rc + skin is reused while no atom has moved
+ *                  more than skin/2 from where the list was built
+ *   max_neighbours capacity of each atom's list; an atom whose list would
+ *                  overflow falls back to a scan over all atoms (still exact) */
+typedef struct pamd_tuning {
+  int32_t algo;
+  int32_t block;
+  int32_t tile;
+  int32_t max_neighbours;
+  double skin;
+} pamd_tuning;
+
+/* Bytes of workspace needed by pamd_action / pamd_action_grad /
+ * pamd_excess_action for this problem and tuning.  Host-only; no device
+ * is touched. */
+int pamd_workspace_size(const pamd_path* path, const pamd_potential* pot,
+                        const pamd_tuning* tuning, size_t* bytes);
+
+/* Action S[X] (Eq. 4 without normalisation).
+ *   x         device, (N+1) * n_dim * n_atoms float64, layout above
+ *   action    device, 1 float64 (written)
+ *   per_step  device, N float64 (written: s_n), or NULL */
+int pamd_action(const pamd_path* path, const pamd_potential* pot, const pamd_tuning* tuning,
+                const double* x, double* action, double* per_step,
+                void* ws, size_t ws_bytes, void* stream);
+
+/* Action and its gradient with respect to every slice (including the
+ * fixed x_0; callers that hold slices fixed mask them).
+ *   step_weights device, N float64, or NULL (= all ones): the gradient is
+ *                that of sum_n w_n s_n; action and per_step stay unweighted
+ *   action       device, 1 float64, or NULL
+ *   per_step     device, N float64, or NULL
+ *   grad         device, same shape as x (written) */
+int pamd_action_grad(const pamd_path* path, const pamd_potential* pot, const pamd_tuning* tuning,
+                     const double* x, const double* step_weights,
+                     double* action, double* per_step, double* grad,
+                     void* ws, size_t ws_bytes, void* stream);
+
+/* Per-step excess action e_n = s_n - s0_n, where s0_n = |Delta_n|^2/(4 D dt)
+ * is the force-free (free-particle) term: the quantity the fragment-wise
+ * Metropolis-Hastings test needs (Sec. III).  e_n is evaluated as
+ * sum (r - Delta)(r + Delta) / (4 D dt) to avoid cancellation.
+ *   excess    device, N float64 (written)
+ *   per_step  device, N float64 (written: s_n) or NULL */
+int pamd_excess_action(const pamd_path* path, const pamd_potential* pot, const pamd_tuning* tuning,
+                       const double* x, double* excess, double* per_step,
+                       void* ws, size_t ws_bytes, void* stream);
+
+/* Normalisation omitted from S: N * (n_dim * n_atoms / 2) * ln(4 pi D dt), so
+ * that -ln prod_n K(x_{n+1}|x_n; dt) = S + pamd_log_norm(path) (Eq. 3 with its
+ * Gaussian normalisation).  Returns NaN for an invalid path. */
+double pamd_log_norm(const pamd_path* path);
+
+/* Message of the calling thread's last failed call ("" if none). */
+const char* pamd_last_error(void);
+
+/* Library version string. */
+const char* pamd_version(void);
+
+/* ------------------------------------------------------------------------
+ * Batches: many independent paths (different N, n_atoms, dt, potential) in
+ * one persistent launch for all Lennard-Jones members plus one launch for all
+ * harmonic members.  A batch is a host object describing the members; its
+ * buffers are packed: member p's path starts at element x_offsets[p] of one
+ * device array (offsets are multiples of 32 elements), and the same offsets
+ * index the packed gradient.  Per-step outputs are packed at step_offsets[p].
+ * All members must share one precision.
+ * ---------------------------------------------------------------------- */
+typedef struct pamd_batch pamd_batch;
+
+int pamd_batch_create(int32_t n_paths, const pamd_path* paths /* host, n_paths */,
+                      const pamd_potential* pots /* host, n_paths */,
+                      const pamd_tuning* tuning, pamd_batch** out);
+void pamd_batch_destroy(pamd_batch* batch);
+
+/* Packed layout: x_offsets and step_offsets are host arrays of n_paths + 1
+ * int64 (the last entry is the total), either may be NULL.  ws_bytes gets the
+ * workspace size. */
+int pamd_batch_layout(const pamd_batch* batch, int64_t* x_offsets, int64_t* step_offsets,
+                      size_t* ws_bytes);
+
+/* Uploads the batch's work list into `ws` (one host-to-device copy).  Call once
+ * per workspace before pamd_batch_action_grad, outside any graph capture; the
+ * workspace then stays valid for any number of calls on this batch. */
+int pamd_batch_prepare(const pamd_batch* batch, void* ws, size_t ws_bytes, void* stream);
+
+/* Actions (and gradients) of every member.
+ *   x_all        device, packed paths
+ *   weights_all  device, packed per-step weights, or NULL (= all ones)
+ *   actions      device, n_paths float64 (written)
+ *   per_step_all device, packed per-step actions, or NULL
+ *   grad_all     device, packed gradients, or NULL for actions only */
+int pamd_batch_action_grad(const pamd_batch* batch, const double* x_all,
+                           const double* weights_all, double* actions, double* per_step_all,
+                           double* grad_all, void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Path sampling (Sec. III): one Monte Carlo step of the multilevel sliding-
+ * and-sampling move with free-particle trial paths.
+ *   1. level l uniform in [l_min, l_max], offset u uniform in [1, 2^l];
+ *      fragment endpoints u, u + 2^l, ... <= N; the tail fragment is [0, u],
+ *      internal fragments span 2^l steps, a nose fragment [e_last, N] exists
+ *      when e_last < N (random fragmentation, Fig. 5);
+ *   2. every fragment draws a free-particle trial with its endpoints fixed
+ *      (Brownian bridge, per-step variance 2 D dt; the nose fragment continues
+ *      freely and also moves x_N); x_0 never moves;
+ *   3. fragment f is accepted when u_f < exp(-Delta_f),
+ *      Delta_f = sum_{n in f} (e'_n - e_n), e = excess action (see
+ *      pamd_excess_action), primes for the trial path;
+ *   4. accepted fragments are copied into x and their e_n into `excess`.
+ * Random numbers: Philox4x32-10 with key (seed mod 2^32, seed >> 32):
+ *   level/offset    counter (0, 0, s, 1): l = l_min + w0 mod (l_max - l_min + 1),
+ *                   u = 1 + w1 mod 2^l
+ *   accept uniform  counter (f, 0, s, 2): ((w0 >> 6) 2^26 + (w1 >> 6) + 1/2) 2^-52
+ *   trial normal    counter (p mod 2^32, p >> 32, s, 3), p = e >> 1 for flat element
+ *                   index e = n * n_dim * n_atoms + k; Box-Muller of the two
+ *                   uniforms (w0,w1), (w2,w3); even e takes the cosine output,
+ *                   odd e the sine output
+ * where s is the sweep index read from *sweep_counter (device int64), which
+ * the call increments, so a captured graph replays successive sweeps.
+ * ---------------------------------------------------------------------- */
+int pamd_mh_workspace_size(const pamd_path* path, const pamd_potential* pot,
+                           const pamd_tuning* tuning, size_t* bytes);
+
+/*   x             device path (read and updated in place)
+ *   excess        device, N float64: e_n of x on entry, updated on exit
+ *   trial         device scratch, same shape as x (holds the trial path on exit)
+ *   frag_delta    device, N + 2 float64 (Delta_f by fragment), or NULL
+ *   frag_accept   device, N + 2 int32 (1 accepted, 0 rejected), or NULL
+ *   step_info     device, 4 int32 {l, u, n_fragments, n_accepted}, or NULL
+ *   requires 1 <= l_min <= l_max and 2^l_max <= N. */
+int pamd_mh_step(const pamd_path* path, const pamd_potential* pot, const pamd_tuning* tuning,
+                 uint64_t seed, int32_t l_min, int32_t l_max, int64_t* sweep_counter,
+                 double* x, double* excess, double* trial,
+                 double* frag_delta, int32_t* frag_accept, int32_t* step_info,
+                 void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Autotuning: times candidate (block, tile, skin) choices for this problem on
+ * the given inputs and caches the fastest for later calls with the same
+ * (potential kind, n_atoms, cells per axis, precision) key.  Synchronises the
+ * stream.  `best` (host, may be NULL) receives the choice.
+ * ---------------------------------------------------------------------- */
+int pamd_autotune(const pamd_path* path, const pamd_potential* pot, const double* x,
+                  double* grad_scratch, void* ws, size_t ws_bytes, void* stream,
+                  pamd_tuning* best);
+
+/* ------------------------------------------------------------------------
+ * Measurement hook: the next pamd_action / pamd_action_grad /
+ * pamd_excess_action call made by this thread records `start` (a hipEvent_t)
+ * on its stream just before its main kernel and `stop` just after it, so that
+ * the events bracket that kernel alone.  Host-only; pass NULLs to clear.
+ * ---------------------------------------------------------------------- */
+int pamd_profile_events(void* start, void* stop);
+
+/* ------------------------------------------------------------------------
+ * HIP graph helpers: capture any sequence of pamd_* calls enqueued on
+ * `stream` between begin and end, then replay it.
+ * ---------------------------------------------------------------------- */
+typedef struct pamd_graph pamd_graph;
+int pamd_graph_begin(void* stream);
+int pamd_graph_end(void* stream, pamd_graph** out);
+int pamd_graph_launch(const pamd_graph* graph, void* stream);
+void pamd_graph_destroy(pamd_graph* graph);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PAMD_H */

@@ -1,0 +1,249 @@
+"""Python binding of libpamd with the C entry points' names.
+
+Every function marshals torch tensors (device pointers, the current HIP
+stream) into the C ABI and raises ``PamdError`` on failure; all arithmetic
+runs in the library's HIP kernels.  Paths are float64 tensors of shape
+(n_steps + 1, n_dim, n_atoms), contiguous, on the current HIP device.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+from typing import Optional, Sequence
+
+import torch
+
+from . import _lib
+from ._lib import (PamdPath, PamdPotential, PamdTuning, PamdError, PAMD_HARMONIC, PAMD_LJ,
+                   PAMD_FP64, PAMD_FP32_FORCE, PAMD_ALGO_AUTO, PAMD_ALGO_FUSED,
+                   PAMD_ALGO_PLAIN)
+
+__all__ = [
+    "PamdPath", "PamdPotential", "PamdTuning", "PamdError", "make_path", "make_potential",
+    "make_tuning", "pamd_workspace_size", "pamd_action", "pamd_action_grad",
+    "pamd_excess_action", "pamd_log_norm", "pamd_mh_workspace_size", "pamd_mh_step",
+    "pamd_autotune", "PamdBatch", "PamdGraph", "workspace",
+]
+
+
+# ---------------------------------------------------------------------------
+# descriptors
+# ---------------------------------------------------------------------------
+def make_path(n_steps: int, n_atoms: int, n_dim: int, dt: float, D: float, gamma: float,
+              precision: str = "fp64") -> PamdPath:
+    prec = {"fp64": PAMD_FP64, "fp32_force": PAMD_FP32_FORCE}[precision]
+    return PamdPath(int(n_steps), int(n_atoms), int(n_dim), float(dt), float(D), float(gamma),
+                    prec, 0)
+
+
+def make_potential(kind: str, k: float = 1.0, eps: float = 1.0, sigma: float = 1.0,
+                   rc: float = 2.5, box: float = 0.0) -> PamdPotential:
+    if kind == "harmonic":
+        return PamdPotential(PAMD_HARMONIC, 0, float(k), 0.0, 0.0, 0.0, 0.0)
+    if kind == "lj":
+        return PamdPotential(PAMD_LJ, 0, 0.0, float(eps), float(sigma), float(rc), float(box))
+    raise ValueError(kind)
+
+
+def make_tuning(algo: str = "auto", block: int = 0, tile: int = 0, max_neighbours: int = 0,
+                skin: float = 0.0) -> PamdTuning:
+    a = {"auto": PAMD_ALGO_AUTO, "fused": PAMD_ALGO_FUSED, "plain": PAMD_ALGO_PLAIN}[algo]
+    return PamdTuning(a, int(block), int(tile), int(max_neighbours), float(skin))
+
+
+def _ref(s):
+    return ctypes.byref(s) if s is not None else None
+
+
+def _ptr(t: Optional[torch.Tensor], dtype=torch.float64, name: str = "tensor"):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream) -> ctypes.c_void_p:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+def workspace(nbytes: int, device=None) -> torch.Tensor:
+    """Device buffer for a workspace (allocated by torch, never by the library)."""
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8,
+                       device=device if device is not None else torch.cuda.current_device())
+
+
+# ---------------------------------------------------------------------------
+# single paths
+# ---------------------------------------------------------------------------
+def pamd_workspace_size(path: PamdPath, pot: PamdPotential,
+                        tuning: Optional[PamdTuning] = None) -> int:
+    n = ctypes.c_size_t(0)
+    _lib.call("pamd_workspace_size", ctypes.byref(path), ctypes.byref(pot), _ref(tuning),
+              ctypes.byref(n))
+    return int(n.value)
+
+
+def _ws(path, pot, tuning, ws, sizer=pamd_workspace_size):
+    need = sizer(path, pot, tuning)
+    if ws is None:
+        ws = workspace(need)
+    return ws, need
+
+
+def pamd_action(path, pot, x, action, per_step=None, ws=None, tuning=None, stream=None):
+    ws, _ = _ws(path, pot, tuning, ws)
+    _lib.call("pamd_action", ctypes.byref(path), ctypes.byref(pot), _ref(tuning),
+              _ptr(x, name="x"), _ptr(action, name="action"), _ptr(per_step, name="per_step"),
+              _ptr(ws, None, "ws"), ctypes.c_size_t(ws.numel()), _stream(stream))
+
+
+def pamd_action_grad(path, pot, x, grad, action=None, per_step=None, step_weights=None,
+                     ws=None, tuning=None, stream=None):
+    ws, _ = _ws(path, pot, tuning, ws)
+    _lib.call("pamd_action_grad", ctypes.byref(path), ctypes.byref(pot), _ref(tuning),
+              _ptr(x, name="x"), _ptr(step_weights, name="step_weights"),
+              _ptr(action, name="action"), _ptr(per_step, name="per_step"),
+              _ptr(grad, name="grad"), _ptr(ws, None, "ws"), ctypes.c_size_t(ws.numel()),
+              _stream(stream))
+
+
+def pamd_excess_action(path, pot, x, excess, per_step=None, ws=None, tuning=None, stream=None):
+    ws, _ = _ws(path, pot, tuning, ws)
+    _lib.call("pamd_excess_action", ctypes.byref(path), ctypes.byref(pot), _ref(tuning),
+              _ptr(x, name="x"), _ptr(excess, name="excess"), _ptr(per_step, name="per_step"),
+              _ptr(ws, None, "ws"), ctypes.c_size_t(ws.numel()), _stream(stream))
+
+
+def pamd_log_norm(path: PamdPath) -> float:
+    return float(_lib.load().pamd_log_norm(ctypes.byref(path)))
+
+
+# ---------------------------------------------------------------------------
+# path sampling
+# ---------------------------------------------------------------------------
+def pamd_mh_workspace_size(path, pot, tuning=None) -> int:
+    n = ctypes.c_size_t(0)
+    _lib.call("pamd_mh_workspace_size", ctypes.byref(path), ctypes.byref(pot), _ref(tuning),
+              ctypes.byref(n))
+    return int(n.value)
+
+
+def pamd_mh_step(path, pot, seed: int, l_min: int, l_max: int, sweep_counter: torch.Tensor,
+                 x: torch.Tensor, excess: torch.Tensor, trial: torch.Tensor,
+                 frag_delta=None, frag_accept=None, step_info=None, ws=None, tuning=None,
+                 stream=None):
+    ws, _ = _ws(path, pot, tuning, ws, pamd_mh_workspace_size)
+    _lib.call("pamd_mh_step", ctypes.byref(path), ctypes.byref(pot), _ref(tuning),
+              ctypes.c_uint64(seed), ctypes.c_int32(l_min), ctypes.c_int32(l_max),
+              _ptr(sweep_counter, torch.int64, "sweep_counter"), _ptr(x, name="x"),
+              _ptr(excess, name="excess"), _ptr(trial, name="trial"),
+              _ptr(frag_delta, name="frag_delta"), _ptr(frag_accept, torch.int32, "frag_accept"),
+              _ptr(step_info, torch.int32, "step_info"), _ptr(ws, None, "ws"),
+              ctypes.c_size_t(ws.numel()), _stream(stream))
+
+
+def pamd_autotune(path, pot, x, grad_scratch, ws, stream=None) -> PamdTuning:
+    best = PamdTuning()
+    _lib.call("pamd_autotune", ctypes.byref(path), ctypes.byref(pot), _ptr(x, name="x"),
+              _ptr(grad_scratch, name="grad_scratch"), _ptr(ws, None, "ws"),
+              ctypes.c_size_t(ws.numel()), _stream(stream), ctypes.byref(best))
+    return best
+
+
+# ---------------------------------------------------------------------------
+# batches and graphs
+# ---------------------------------------------------------------------------
+class PamdBatch:
+    """A batch of independent paths packed into single device buffers."""
+
+    def __init__(self, paths: Sequence[PamdPath], pots: Sequence[PamdPotential],
+                 tuning: Optional[PamdTuning] = None):
+        n = len(paths)
+        self.n_paths = n
+        self._paths = (PamdPath * n)(*paths)
+        self._pots = (PamdPotential * n)(*pots)
+        handle = ctypes.c_void_p()
+        _lib.call("pamd_batch_create", ctypes.c_int32(n), self._paths, self._pots, _ref(tuning),
+                  ctypes.byref(handle))
+        self._h = handle
+        xo = (ctypes.c_int64 * (n + 1))()
+        so = (ctypes.c_int64 * (n + 1))()
+        nb = ctypes.c_size_t(0)
+        _lib.call("pamd_batch_layout", self._h, xo, so, ctypes.byref(nb))
+        self.x_offsets = list(xo)
+        self.step_offsets = list(so)
+        self.ws_bytes = int(nb.value)
+        self.ws = None
+
+    def prepare(self, ws: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+        if ws is None:
+            ws = workspace(self.ws_bytes)
+        _lib.call("pamd_batch_prepare", self._h, _ptr(ws, None, "ws"), ctypes.c_size_t(ws.numel()),
+                  _stream(stream))
+        self.ws = ws
+        return ws
+
+    def pamd_batch_action_grad(self, x_all, actions, grad_all=None, per_step_all=None,
+                               weights_all=None, stream=None):
+        if self.ws is None:
+            self.prepare(stream=stream)
+        _lib.call("pamd_batch_action_grad", self._h, _ptr(x_all, name="x_all"),
+                  _ptr(weights_all, name="weights_all"), _ptr(actions, name="actions"),
+                  _ptr(per_step_all, name="per_step_all"), _ptr(grad_all, name="grad_all"),
+                  _ptr(self.ws, None, "ws"), ctypes.c_size_t(self.ws.numel()), _stream(stream))
+
+    def view(self, packed: torch.Tensor, p: int) -> torch.Tensor:
+        """Member p's path (or gradient) inside a packed buffer, shaped (N+1, n_dim, n_atoms)."""
+        pp = self._paths[p]
+        n = (pp.n_steps + 1) * pp.n_dim * pp.n_atoms
+        o = self.x_offsets[p]
+        return packed[o:o + n].view(pp.n_steps + 1, pp.n_dim, pp.n_atoms)
+
+    def steps_view(self, packed: torch.Tensor, p: int) -> torch.Tensor:
+        o = self.step_offsets[p]
+        return packed[o:o + self._paths[p].n_steps]
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.load().pamd_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class PamdGraph:
+    """Captures the pamd_* calls enqueued on a stream between begin() and end()."""
+
+    def __init__(self):
+        self._h = ctypes.c_void_p()
+
+    def begin(self, stream):
+        _lib.call("pamd_graph_begin", _stream(stream))
+
+    def end(self, stream):
+        _lib.call("pamd_graph_end", _stream(stream), ctypes.byref(self._h))
+
+    def launch(self, stream):
+        _lib.call("pamd_graph_launch", self._h, _stream(stream))
+
+    def close(self):
+        if self._h.value:
+            _lib.load().pamd_graph_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

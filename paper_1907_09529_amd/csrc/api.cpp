@@ -1,0 +1,654 @@
+// C ABI of libpamd: argument validation, launch planning, workspace layout,
+// dispatch, batches, path sampling, autotuning and graph capture.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "internal.hpp"
+#include "pamd.h"
+
+using namespace pamd;
+
+namespace {
+
+thread_local std::string g_err;
+thread_local hipEvent_t g_ev_start = nullptr, g_ev_stop = nullptr;
+
+// Records the one-shot measurement events around the main kernel of a call.
+struct EventScope {
+  hipStream_t st;
+  hipEvent_t a, b;
+  explicit EventScope(hipStream_t s) : st(s), a(g_ev_start), b(g_ev_stop) {
+    g_ev_start = g_ev_stop = nullptr;
+    if (a) hipEventRecord(a, st);
+  }
+  ~EventScope() {
+    if (b) hipEventRecord(b, st);
+  }
+};
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define PAMD_HIP(expr)                                                                 \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess) return fail(PAMD_EHIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+constexpr size_t kLdsMax = 163840;  // LDS per workgroup on gfx950
+constexpr int kMaxGrid = 2048;      // persistent-grid cap: bounds per-block scratch
+constexpr size_t kAlign = 256;
+constexpr double kDefaultSkin = 0.3;  // in units of sigma
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+// ---------------------------------------------------------------------------
+// Validation
+// ---------------------------------------------------------------------------
+int check_path(const pamd_path* p) {
+  if (!p) return fail(PAMD_EINVAL, "path is NULL");
+  if (p->n_steps < 1) return fail(PAMD_EINVAL, "n_steps must be >= 1 (got %lld)", (long long)p->n_steps);
+  if (p->n_atoms < 1) return fail(PAMD_EINVAL, "n_atoms must be >= 1 (got %d)", p->n_atoms);
+  if (p->n_dim != 1 && p->n_dim != 3)
+    return fail(PAMD_EUNSUPPORTED, "n_dim must be 1 or 3 (got %d)", p->n_dim);
+  if (!finite_pos(p->dt)) return fail(PAMD_EINVAL, "dt must be finite and > 0");
+  if (!finite_pos(p->D)) return fail(PAMD_EINVAL, "D must be finite and > 0");
+  if (!finite_pos(p->gamma)) return fail(PAMD_EINVAL, "gamma must be finite and > 0");
+  if (p->precision != PAMD_FP64 && p->precision != PAMD_FP32_FORCE)
+    return fail(PAMD_EINVAL, "precision must be PAMD_FP64 or PAMD_FP32_FORCE (got %d)", p->precision);
+  const double elems = (double)(p->n_steps + 1) * p->n_dim * p->n_atoms;
+  if (elems > 9.0e15) return fail(PAMD_EINVAL, "path too large");
+  return PAMD_OK;
+}
+
+int check_pot(const pamd_path* p, const pamd_potential* v) {
+  if (!v) return fail(PAMD_EINVAL, "potential is NULL");
+  if (v->kind == PAMD_HARMONIC) {
+    if (!std::isfinite(v->k)) return fail(PAMD_EINVAL, "harmonic k must be finite");
+    if (v->box != 0.0) return fail(PAMD_EUNSUPPORTED, "harmonic potential takes no periodic box (box must be 0)");
+    return PAMD_OK;
+  }
+  if (v->kind != PAMD_LJ) return fail(PAMD_EINVAL, "unknown potential kind %d", v->kind);
+  if (p->n_dim != 3) return fail(PAMD_EUNSUPPORTED, "Lennard-Jones paths need n_dim = 3 (got %d)", p->n_dim);
+  if (!finite_pos(v->eps)) return fail(PAMD_EINVAL, "eps must be finite and > 0");
+  if (!finite_pos(v->sigma)) return fail(PAMD_EINVAL, "sigma must be finite and > 0");
+  if (!finite_pos(v->rc)) return fail(PAMD_EINVAL, "rc must be finite and > 0");
+  if (!finite_pos(v->box)) return fail(PAMD_EINVAL, "box must be finite and > 0");
+  if (v->rc > 0.5 * v->box)
+    return fail(PAMD_EUNSUPPORTED, "rc = %g exceeds half the box (%g): minimum image would miss pairs", v->rc, 0.5 * v->box);
+  if (p->n_atoms > 65535) return fail(PAMD_EUNSUPPORTED, "Lennard-Jones paths support at most 65535 atoms");
+  return PAMD_OK;
+}
+
+int check_tuning(const pamd_tuning* t) {
+  if (!t) return PAMD_OK;
+  if (t->algo < PAMD_ALGO_AUTO || t->algo > PAMD_ALGO_PLAIN) return fail(PAMD_EINVAL, "unknown algo %d", t->algo);
+  if (t->block != 0 && (t->block < 64 || t->block > 1024 || t->block % 64))
+    return fail(PAMD_EINVAL, "block must be 0 or a multiple of 64 in [64, 1024] (got %d)", t->block);
+  if (t->tile < 0) return fail(PAMD_EINVAL, "tile must be >= 0");
+  if (t->max_neighbours < 0) return fail(PAMD_EINVAL, "max_neighbours must be >= 0");
+  if (!std::isfinite(t->skin)) return fail(PAMD_EINVAL, "skin must be finite");
+  return PAMD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Autotune cache
+// ---------------------------------------------------------------------------
+std::mutex g_tune_mu;
+std::map<std::string, pamd_tuning> g_tune;
+
+std::string tune_key(const pamd_path* p, const pamd_potential* v) {
+  char buf[160];
+  int lg = 0;
+  while (((int64_t)1 << (lg + 1)) <= p->n_steps) ++lg;
+  snprintf(buf, sizeof(buf), "%d/%d/%d/%d/%.6g/%.6g", v->kind, p->n_atoms, p->precision, lg,
+           v->kind == PAMD_LJ ? v->box : 0.0, v->kind == PAMD_LJ ? v->rc : 0.0);
+  return buf;
+}
+
+bool cached_tuning(const pamd_path* p, const pamd_potential* v, pamd_tuning* out) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  auto it = g_tune.find(tune_key(p, v));
+  if (it == g_tune.end()) return false;
+  *out = it->second;
+  return true;
+}
+
+// ---------------------------------------------------------------------------
+// Planning
+// ---------------------------------------------------------------------------
+struct CellGrid {
+  int nc = 0, reach = 0;
+};
+
+// Cells of edge >= radius / reach, stencil of (2 reach + 1)^3 distinct cells;
+// the variant visiting fewer candidate atoms wins; nc = 0 means all pairs.
+CellGrid choose_cells(double box, double radius, int n_atoms) {
+  CellGrid g;
+  const double rho = n_atoms / (box * box * box);
+  double best = (double)n_atoms;  // all pairs
+  const int cap = std::max(64, 4 * n_atoms);
+  for (int reach = 1; reach <= 2; ++reach) {
+    int nc = (int)std::floor(reach * box / radius);
+    while (nc >= 2 * reach + 1 && (int64_t)nc * nc * nc > cap) --nc;
+    if (nc < 2 * reach + 1) continue;
+    const double h = box / nc;
+    const double cand = std::pow(2 * reach + 1, 3) * h * h * h * rho;
+    if (cand < best) {
+      best = cand;
+      g.nc = nc;
+      g.reach = reach;
+    }
+  }
+  return g;
+}
+
+int default_kmax(double box, double radius, int n_atoms) {
+  const double rho = n_atoms / (box * box * box);
+  const double expect = 4.0 / 3.0 * M_PI * radius * radius * radius * rho;
+  int k = (int)align_up((size_t)std::ceil(1.3 * expect + 24.0), 8);
+  return std::max(1, std::min(k, n_atoms - 1 > 0 ? n_atoms - 1 : 1));
+}
+
+int default_block(int n_atoms) {
+  int b = n_atoms <= 512 ? (int)align_up((size_t)n_atoms, 64)
+                         : (int)align_up((size_t)((n_atoms + 1) / 2), 64);
+  return std::max(64, std::min(1024, b));
+}
+
+struct Plan {
+  int kind = 0;
+  bool f32 = false;
+  int algo = PAMD_ALGO_FUSED;
+  int64_t steps = 0;
+  int N = 0, dim = 0;
+  int64_t dof = 0;
+  // fused LJ
+  int block = 0, tile = 0, n_tiles = 0, grid = 0, kmax = 0;
+  CellGrid cells;
+  double skin = 0;
+  bool r_in_lds = true;
+  size_t lds = 0;
+  // plain LJ
+  CellGrid pcells;
+  int pkmax = 0;
+  size_t plds = 0;
+  // harmonic
+  int seg = 1;
+  // workspace (byte offsets)
+  size_t off_step = 0, off_bnd = 0, off_nbr = 0, off_cnt = 0, off_xref = 0, off_rglob = 0;
+  size_t nbr_stride = 0, cnt_stride = 0, xref_stride = 0, rglob_stride = 0;  // elements
+  size_t off_pnbr = 0, off_pcnt = 0, off_F = 0, off_R = 0, off_Q = 0;
+  size_t off_mh_ex = 0, off_mh_state = 0, off_mh_acc = 0;
+  size_t total = 0;
+};
+
+size_t bump(size_t& cur, size_t bytes) {
+  const size_t at = align_up(cur, kAlign);
+  cur = at + bytes;
+  return at;
+}
+
+int make_plan(const pamd_path* p, const pamd_potential* v, const pamd_tuning* t_in, bool mh,
+              Plan& P) {
+  int rc;
+  if ((rc = check_path(p)) || (rc = check_pot(p, v)) || (rc = check_tuning(t_in))) return rc;
+  pamd_tuning t{};
+  if (t_in) t = *t_in;
+  pamd_tuning cached{};
+  const bool have_cache = cached_tuning(p, v, &cached);
+  P.kind = v->kind;
+  P.steps = p->n_steps;
+  P.N = p->n_atoms;
+  P.dim = p->n_dim;
+  P.dof = (int64_t)p->n_dim * p->n_atoms;
+  P.f32 = v->kind == PAMD_LJ && p->precision == PAMD_FP32_FORCE;
+  P.algo = t.algo == PAMD_ALGO_PLAIN ? PAMD_ALGO_PLAIN : PAMD_ALGO_FUSED;
+  size_t cur = 0;
+  P.off_step = bump(cur, sizeof(double) * P.steps);
+  if (v->kind == PAMD_HARMONIC) {
+    int seg = 1;
+    while (seg < 64 && seg < P.dof) seg <<= 1;
+    P.seg = seg;
+  } else if (P.algo == PAMD_ALGO_FUSED) {
+    const int N = P.N;
+    const double L = v->box;
+    P.skin = t.skin > 0 ? t.skin : (have_cache && cached.skin > 0 ? cached.skin : kDefaultSkin * v->sigma);
+    const double radius = v->rc + P.skin;
+    P.cells = choose_cells(L, radius, N);
+    P.kmax = t.max_neighbours > 0 ? std::min(t.max_neighbours, std::max(1, N - 1))
+                                  : default_kmax(L, radius, N);
+    P.block = t.block ? t.block : (have_cache && cached.block ? cached.block : default_block(N));
+    int tile = t.tile ? t.tile : (have_cache && cached.tile ? cached.tile : 0);
+    if (tile <= 0) tile = (int)std::max<int64_t>(1, std::min<int64_t>(32, P.steps / 512));
+    P.tile = (int)std::min<int64_t>(tile, P.steps);
+    P.n_tiles = (int)((P.steps + P.tile - 1) / P.tile);
+    P.grid = std::min(P.n_tiles, kMaxGrid);
+    const size_t lds_r = fused_lds_bytes(N, P.cells.nc, true);
+    const size_t lds_g = fused_lds_bytes(N, P.cells.nc, false);
+    if (lds_r <= kLdsMax) {
+      P.r_in_lds = true;
+      P.lds = lds_r;
+    } else if (lds_g <= kLdsMax) {
+      P.r_in_lds = false;
+      P.lds = lds_g;
+    } else {
+      return fail(PAMD_EUNSUPPORTED, "n_atoms = %d needs %zu bytes of LDS per workgroup (max %zu)", N, lds_g, kLdsMax);
+    }
+    P.off_bnd = bump(cur, sizeof(double) * 3 * N * (size_t)std::max(0, P.n_tiles - 1));
+    P.nbr_stride = align_up((size_t)P.kmax * N, 128);
+    P.cnt_stride = align_up((size_t)N, 64);
+    P.xref_stride = align_up((size_t)6 * N, 32);
+    P.rglob_stride = P.r_in_lds ? 0 : align_up((size_t)3 * N, 32);
+    P.off_nbr = bump(cur, sizeof(uint16_t) * P.nbr_stride * P.grid);
+    P.off_cnt = bump(cur, sizeof(int32_t) * P.cnt_stride * P.grid);
+    P.off_xref = bump(cur, sizeof(double) * P.xref_stride * P.grid);
+    P.off_rglob = bump(cur, sizeof(double) * P.rglob_stride * P.grid);
+  } else {
+    const int N = P.N;
+    P.pcells = choose_cells(v->box, v->rc, N);
+    P.pkmax = t.max_neighbours > 0 ? std::min(t.max_neighbours, std::max(1, N - 1))
+                                   : default_kmax(v->box, v->rc, N);
+    P.block = t.block ? t.block : 256;
+    P.plds = plain_lds_bytes(N, P.pcells.nc);
+    if (P.plds > kLdsMax)
+      return fail(PAMD_EUNSUPPORTED, "plain form: n_atoms = %d needs %zu bytes of LDS (max %zu)", N, P.plds, kLdsMax);
+    const size_t S = (size_t)P.steps;
+    P.off_pnbr = bump(cur, sizeof(uint16_t) * S * P.pkmax * N);
+    P.off_pcnt = bump(cur, sizeof(int32_t) * S * N);
+    P.off_F = bump(cur, sizeof(double) * S * 3 * N);
+    P.off_R = bump(cur, sizeof(double) * S * 3 * N);
+    P.off_Q = bump(cur, sizeof(double) * S * 3 * N);
+  }
+  if (mh) {
+    P.off_mh_ex = bump(cur, sizeof(double) * P.steps);
+    P.off_mh_state = bump(cur, sizeof(int32_t) * 4);
+    P.off_mh_acc = bump(cur, sizeof(int32_t) * (P.steps + 2));
+  }
+  P.total = align_up(cur, kAlign);
+  return PAMD_OK;
+}
+
+int check_ws(const Plan& P, void* ws, size_t ws_bytes) {
+  if (ws_bytes < P.total)
+    return fail(PAMD_EWORKSPACE, "workspace has %zu bytes, %zu needed", ws_bytes, P.total);
+  if (P.total && !ws) return fail(PAMD_EINVAL, "workspace is NULL");
+  if (((uintptr_t)ws) % kAlign) return fail(PAMD_EWORKSPACE, "workspace must be 256-byte aligned");
+  return PAMD_OK;
+}
+
+template <typename T>
+T* at(void* ws, size_t off) {
+  return reinterpret_cast<T*>(reinterpret_cast<char*>(ws) + off);
+}
+
+void fill_lj(const pamd_path* p, const pamd_potential* v, const Plan& P, PathArgs& a) {
+  std::memset(&a, 0, sizeof(a));
+  a.n_steps = p->n_steps;
+  a.n_atoms = p->n_atoms;
+  a.tile = P.tile;
+  a.n_tiles = P.n_tiles;
+  a.mu_dt = p->dt / p->gamma;
+  a.inv4Ddt = 1.0 / (4.0 * p->D * p->dt);
+  a.c = 1.0 / (2.0 * p->D * p->dt);
+  a.lj.box = v->box;
+  a.lj.inv_box = 1.0 / v->box;
+  a.lj.rc2 = v->rc * v->rc;
+  a.lj.a24 = 24.0 * v->eps;
+  a.lj.sig2 = v->sigma * v->sigma;
+  const double sr = v->sigma / v->rc;
+  const double sr6 = sr * sr * sr * sr * sr * sr;
+  a.lj.duc = -(24.0 * v->eps / v->rc) * (2.0 * sr6 * sr6 - sr6);  // u'(r_c)
+  const double radius = v->rc + P.skin;
+  a.rlist2 = radius * radius;
+  a.half_skin2 = 0.25 * P.skin * P.skin;
+  a.nc = P.cells.nc;
+  a.reach = P.cells.reach;
+  a.kmax = P.kmax;
+}
+
+BlockScratch scratch_of(const Plan& P, void* ws) {
+  BlockScratch s;
+  s.nbr = at<uint16_t>(ws, P.off_nbr);
+  s.cnt = at<int32_t>(ws, P.off_cnt);
+  s.xref = at<double>(ws, P.off_xref);
+  s.rglob = P.r_in_lds ? nullptr : at<double>(ws, P.off_rglob);
+  s.nbr_stride = (int64_t)P.nbr_stride;
+  s.cnt_stride = (int64_t)P.cnt_stride;
+  s.xref_stride = (int64_t)P.xref_stride;
+  s.rglob_stride = (int64_t)P.rglob_stride;
+  return s;
+}
+
+FusedLaunch launch_of(const Plan& P) {
+  FusedLaunch L;
+  L.block = P.block;
+  L.grid = P.grid;
+  L.r_in_lds = P.r_in_lds;
+  L.f32 = P.f32;
+  L.lds_bytes = P.lds;
+  return L;
+}
+
+// Core evaluation shared by the entry points.
+int evaluate(const pamd_path* p, const pamd_potential* v, const Plan& P, const double* x,
+             const double* w, double* action, double* per_step, double* grad, double* excess,
+             int mode, void* ws, hipStream_t st) {
+  double* steps = per_step ? per_step : at<double>(ws, P.off_step);
+  if (P.kind == PAMD_HARMONIC) {
+    HOArgs h;
+    h.x = x;
+    h.weights = w;
+    h.grad = grad;
+    h.per_step = steps;
+    h.excess = excess;
+    h.n_steps = P.steps;
+    h.n_dof = P.dof;
+    h.k = v->k;
+    h.mu_dt = p->dt / p->gamma;
+    h.inv4Ddt = 1.0 / (4.0 * p->D * p->dt);
+    h.c = 1.0 / (2.0 * p->D * p->dt);
+    h.mode = mode;
+    h.seg = P.seg;
+    {
+      EventScope ev(st);
+      PAMD_HIP(launch_ho(h, action, st));
+    }
+    return PAMD_OK;
+  }
+  PathArgs a;
+  fill_lj(p, v, P, a);
+  a.x = x;
+  a.weights = w;
+  a.grad = grad;
+  a.per_step = steps;
+  a.excess = excess;
+  a.mode = mode;
+  if (P.algo == PAMD_ALGO_PLAIN) {
+    PlainArgs pa;
+    pa.p = a;
+    pa.p.nc = P.pcells.nc;
+    pa.p.reach = P.pcells.reach;
+    pa.p.kmax = P.pkmax;
+    pa.nbr = at<uint16_t>(ws, P.off_pnbr);
+    pa.cnt = at<int32_t>(ws, P.off_pcnt);
+    pa.F = at<double>(ws, P.off_F);
+    pa.R = at<double>(ws, P.off_R);
+    pa.Q = at<double>(ws, P.off_Q);
+    {
+      EventScope ev(st);
+      PAMD_HIP(launch_lj_plain(pa, P.block, P.f32, action, st));
+    }
+    return PAMD_OK;
+  }
+  a.bnd = at<double>(ws, P.off_bnd);
+  {
+    EventScope ev(st);
+    PAMD_HIP(launch_lj_fused(a, scratch_of(P, ws), launch_of(P), st));
+  }
+  if (action || (mode & MODE_GRAD)) PAMD_HIP(launch_lj_finalize(a, action, st));
+  return PAMD_OK;
+}
+
+}  // namespace
+
+namespace pamd {
+int batch_fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+}  // namespace pamd
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char* pamd_last_error(void) { return g_err.c_str(); }
+
+const char* pamd_version(void) { return "pamd 0.1 (gfx950)"; }
+
+int pamd_profile_events(void* start, void* stop) {
+  g_ev_start = (hipEvent_t)start;
+  g_ev_stop = (hipEvent_t)stop;
+  return PAMD_OK;
+}
+
+double pamd_log_norm(const pamd_path* p) {
+  if (check_path(p)) return NAN;
+  return (double)p->n_steps * (p->n_dim * (double)p->n_atoms / 2.0) *
+         std::log(4.0 * M_PI * p->D * p->dt);
+}
+
+int pamd_workspace_size(const pamd_path* p, const pamd_potential* v, const pamd_tuning* t,
+                        size_t* bytes) {
+  if (!bytes) return fail(PAMD_EINVAL, "bytes is NULL");
+  Plan P;
+  int rc = make_plan(p, v, t, false, P);
+  if (rc) return rc;
+  *bytes = P.total;
+  return PAMD_OK;
+}
+
+int pamd_action(const pamd_path* p, const pamd_potential* v, const pamd_tuning* t,
+                const double* x, double* action, double* per_step, void* ws, size_t ws_bytes,
+                void* stream) {
+  Plan P;
+  int rc = make_plan(p, v, t, false, P);
+  if (rc) return rc;
+  if (!x) return fail(PAMD_EINVAL, "x is NULL");
+  if (!action) return fail(PAMD_EINVAL, "action is NULL");
+  if ((rc = check_ws(P, ws, ws_bytes))) return rc;
+  return evaluate(p, v, P, x, nullptr, action, per_step, nullptr, nullptr, 0, ws,
+                  (hipStream_t)stream);
+}
+
+int pamd_action_grad(const pamd_path* p, const pamd_potential* v, const pamd_tuning* t,
+                     const double* x, const double* w, double* action, double* per_step,
+                     double* grad, void* ws, size_t ws_bytes, void* stream) {
+  Plan P;
+  int rc = make_plan(p, v, t, false, P);
+  if (rc) return rc;
+  if (!x) return fail(PAMD_EINVAL, "x is NULL");
+  if (!grad) return fail(PAMD_EINVAL, "grad is NULL");
+  if ((rc = check_ws(P, ws, ws_bytes))) return rc;
+  return evaluate(p, v, P, x, w, action, per_step, grad, nullptr, MODE_GRAD, ws,
+                  (hipStream_t)stream);
+}
+
+int pamd_excess_action(const pamd_path* p, const pamd_potential* v, const pamd_tuning* t,
+                       const double* x, double* excess, double* per_step, void* ws,
+                       size_t ws_bytes, void* stream) {
+  Plan P;
+  int rc = make_plan(p, v, t, false, P);
+  if (rc) return rc;
+  if (!x) return fail(PAMD_EINVAL, "x is NULL");
+  if (!excess) return fail(PAMD_EINVAL, "excess is NULL");
+  if ((rc = check_ws(P, ws, ws_bytes))) return rc;
+  return evaluate(p, v, P, x, nullptr, nullptr, per_step, nullptr, excess, MODE_EXCESS, ws,
+                  (hipStream_t)stream);
+}
+
+// ---------------------------------------------------------------------------
+// Path sampling
+// ---------------------------------------------------------------------------
+int pamd_mh_workspace_size(const pamd_path* p, const pamd_potential* v, const pamd_tuning* t,
+                           size_t* bytes) {
+  if (!bytes) return fail(PAMD_EINVAL, "bytes is NULL");
+  Plan P;
+  int rc = make_plan(p, v, t, true, P);
+  if (rc) return rc;
+  *bytes = P.total;
+  return PAMD_OK;
+}
+
+int pamd_mh_step(const pamd_path* p, const pamd_potential* v, const pamd_tuning* t,
+                 uint64_t seed, int32_t l_min, int32_t l_max, int64_t* sweep_counter,
+                 double* x, double* excess, double* trial, double* frag_delta,
+                 int32_t* frag_accept, int32_t* step_info, void* ws, size_t ws_bytes,
+                 void* stream) {
+  Plan P;
+  int rc = make_plan(p, v, t, true, P);
+  if (rc) return rc;
+  if (!x || !excess || !trial || !sweep_counter)
+    return fail(PAMD_EINVAL, "x, excess, trial and sweep_counter must be non-NULL");
+  if (l_min < 1 || l_max < l_min || l_max > 30)
+    return fail(PAMD_EINVAL, "levels must satisfy 1 <= l_min <= l_max <= 30 (got %d, %d)", l_min, l_max);
+  if (((int64_t)1 << l_max) > p->n_steps)
+    return fail(PAMD_EINVAL, "2^l_max = %lld exceeds n_steps = %lld", (long long)1 << l_max, (long long)p->n_steps);
+  if ((rc = check_ws(P, ws, ws_bytes))) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  MHArgs m;
+  m.x = x;
+  m.trial = trial;
+  m.excess = excess;
+  m.excess_trial = at<double>(ws, P.off_mh_ex);
+  m.frag_delta = frag_delta;
+  m.frag_accept = frag_accept;
+  m.step_info = step_info;
+  m.state = at<int32_t>(ws, P.off_mh_state);
+  m.acc_ws = at<int32_t>(ws, P.off_mh_acc);
+  m.sweep_counter = sweep_counter;
+  m.n_steps = p->n_steps;
+  m.n_dof = P.dof;
+  m.key0 = (uint32_t)(seed & 0xffffffffu);
+  m.key1 = (uint32_t)(seed >> 32);
+  m.l_min = l_min;
+  m.l_max = l_max;
+  m.sig = std::sqrt(2.0 * p->D * p->dt);
+  PAMD_HIP(launch_mh_prepare(m, st));
+  PAMD_HIP(launch_mh_trial(m, st));
+  rc = evaluate(p, v, P, trial, nullptr, nullptr, nullptr, nullptr, m.excess_trial, MODE_EXCESS,
+                ws, st);
+  if (rc) return rc;
+  PAMD_HIP(launch_mh_accept(m, st));
+  return PAMD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Autotuning
+// ---------------------------------------------------------------------------
+int pamd_autotune(const pamd_path* p, const pamd_potential* v, const double* x,
+                  double* grad_scratch, void* ws, size_t ws_bytes, void* stream,
+                  pamd_tuning* best) {
+  int rc;
+  if ((rc = check_path(p)) || (rc = check_pot(p, v))) return rc;
+  if (!x || !grad_scratch) return fail(PAMD_EINVAL, "x and grad_scratch must be non-NULL");
+  hipStream_t st = (hipStream_t)stream;
+  std::vector<pamd_tuning> cands;
+  if (v->kind == PAMD_LJ) {
+    const int N = p->n_atoms;
+    std::vector<int> blocks;
+    for (int b : {default_block(N), (int)align_up((size_t)N, 64), (int)align_up((size_t)(N + 3) / 4, 64), 256, 512})
+      if (b >= 64 && b <= 1024 && std::find(blocks.begin(), blocks.end(), b) == blocks.end()) blocks.push_back(b);
+    for (int b : blocks)
+      for (int tile : {2, 4, 8, 16, 32})
+        for (double skin : {0.2, 0.3, 0.45})
+          cands.push_back(pamd_tuning{PAMD_ALGO_FUSED, b, tile, 0, skin * v->sigma});
+  } else {
+    cands.push_back(pamd_tuning{});
+  }
+  hipEvent_t e0, e1;
+  PAMD_HIP(hipEventCreate(&e0));
+  PAMD_HIP(hipEventCreate(&e1));
+  float best_ms = 1e30f;
+  pamd_tuning best_t{};
+  bool found = false;
+  for (const auto& c : cands) {
+    Plan P;
+    if (make_plan(p, v, &c, false, P) != PAMD_OK) continue;
+    if (P.total > ws_bytes || !ws) continue;
+    if (evaluate(p, v, P, x, nullptr, nullptr, nullptr, grad_scratch, nullptr, MODE_GRAD, ws, st))
+      continue;
+    float ms_min = 1e30f;
+    for (int rep = 0; rep < 3; ++rep) {
+      hipEventRecord(e0, st);
+      evaluate(p, v, P, x, nullptr, nullptr, nullptr, grad_scratch, nullptr, MODE_GRAD, ws, st);
+      hipEventRecord(e1, st);
+      if (hipEventSynchronize(e1) != hipSuccess) break;
+      float ms = 0;
+      hipEventElapsedTime(&ms, e0, e1);
+      ms_min = std::min(ms_min, ms);
+    }
+    if (ms_min < best_ms) {
+      best_ms = ms_min;
+      best_t = c;
+      found = true;
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (!found) return fail(PAMD_EWORKSPACE, "no candidate fits the %zu-byte workspace", ws_bytes);
+  best_t.algo = PAMD_ALGO_AUTO;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[tune_key(p, v)] = best_t;
+  }
+  if (best) *best = best_t;
+  return PAMD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Graphs
+// ---------------------------------------------------------------------------
+struct pamd_graph {
+  hipGraph_t graph;
+  hipGraphExec_t exec;
+};
+
+int pamd_graph_begin(void* stream) {
+  if (!stream) return fail(PAMD_EINVAL, "graph capture needs a non-null stream");
+  PAMD_HIP(hipStreamBeginCapture((hipStream_t)stream, hipStreamCaptureModeThreadLocal));
+  return PAMD_OK;
+}
+
+int pamd_graph_end(void* stream, pamd_graph** out) {
+  if (!stream || !out) return fail(PAMD_EINVAL, "stream and out must be non-NULL");
+  hipGraph_t g = nullptr;
+  PAMD_HIP(hipStreamEndCapture((hipStream_t)stream, &g));
+  hipGraphExec_t ex = nullptr;
+  hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    hipGraphDestroy(g);
+    return fail(PAMD_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+  }
+  *out = new pamd_graph{g, ex};
+  return PAMD_OK;
+}
+
+int pamd_graph_launch(const pamd_graph* g, void* stream) {
+  if (!g) return fail(PAMD_EINVAL, "graph is NULL");
+  PAMD_HIP(hipGraphLaunch(g->exec, (hipStream_t)stream));
+  return PAMD_OK;
+}
+
+void pamd_graph_destroy(pamd_graph* g) {
+  if (!g) return;
+  hipGraphExecDestroy(g->exec);
+  hipGraphDestroy(g->graph);
+  delete g;
+}
+
+}  // extern "C"

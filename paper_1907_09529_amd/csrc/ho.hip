@@ -1,0 +1,67 @@
+// Harmonic-oscillator path action and gradient (V = k x^2 / 2 per degree of
+// freedom, Sec. IV A).  Streaming kernel: every element needs x_{n-1}, x_n,
+// x_{n+1} of the same degree of freedom, so one pass over the path computes
+//   r_n = x_{n+1} - x_n + (dt/gamma) k x_n,   s_n = sum r_n^2 / (4 D dt),
+//   g_n = c [w_{n-1} r_{n-1} - w_n r_n (1 - (dt/gamma) k)].
+// `seg` lanes (a power of two <= 64) share a slice; per-slice sums use a
+// fixed xor-butterfly inside the segment.
+#include "device.hpp"
+#include "internal.hpp"
+
+namespace pamd {
+
+__global__ void __launch_bounds__(256) ho_kernel(HOArgs a) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int seg = a.seg;
+  const int per_wave = WAVE / seg;
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
+  const int64_t n_waves = ((int64_t)gridDim.x * blockDim.x) / WAVE;
+  const int sub = lane / seg, sl = lane % seg;
+  const double kmu = a.k * a.mu_dt;
+  for (int64_t base = wave * per_wave; base <= a.n_steps; base += n_waves * per_wave) {
+    const int64_t n = base + sub;
+    const bool valid = n <= a.n_steps;
+    double s_loc = 0.0, e_loc = 0.0;
+    if (valid) {
+      const double w = (a.weights && n < a.n_steps) ? a.weights[n] : 1.0;
+      const double wp = (a.weights && n >= 1) ? a.weights[n - 1] : 1.0;
+      for (int64_t e = sl; e < a.n_dof; e += seg) {
+        const double xn = a.x[n * a.n_dof + e];
+        double g = 0.0;
+        if (n < a.n_steps) {
+          const double d = a.x[(n + 1) * a.n_dof + e] - xn;
+          const double r = fma(kmu, xn, d);
+          s_loc = fma(r, r, s_loc);
+          e_loc = fma(r - d, r + d, e_loc);
+          g = -w * r * (1.0 - kmu);
+        }
+        if (n >= 1) {
+          const double xp = a.x[(n - 1) * a.n_dof + e];
+          const double rp = fma(kmu, xp, xn - xp);
+          g = fma(wp, rp, g);
+        }
+        if (a.mode & MODE_GRAD) a.grad[n * a.n_dof + e] = a.c * g;
+      }
+    }
+    for (int off = seg >> 1; off >= 1; off >>= 1) {
+      s_loc += __shfl_xor(s_loc, off, WAVE);
+      e_loc += __shfl_xor(e_loc, off, WAVE);
+    }
+    if (valid && sl == 0 && n < a.n_steps) {
+      a.per_step[n] = s_loc * a.inv4Ddt;
+      if (a.mode & MODE_EXCESS) a.excess[n] = e_loc * a.inv4Ddt;
+    }
+  }
+}
+
+hipError_t launch_ho(const HOArgs& a, double* action, hipStream_t st) {
+  const int per_wave = WAVE / a.seg;
+  const int64_t waves = (a.n_steps + 1 + per_wave - 1) / per_wave;
+  const int64_t blocks = std::min<int64_t>((waves + 3) / 4, 8192);
+  hipLaunchKernelGGL(ho_kernel, dim3((unsigned)blocks), dim3(256), 0, st, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_sum(a.per_step, a.n_steps, action, st);
+}
+
+}  // namespace pamd

@@ -1,0 +1,158 @@
+// Internal interfaces between the C-ABI layer (api.cpp) and the kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pamd {
+
+// Mode bits of a path evaluation.
+enum : int {
+  MODE_GRAD = 1,     // Hessian-vector pass and gradient
+  MODE_EXCESS = 2,   // per-step excess action e_n = s_n - s0_n
+  MODE_STEP = 4,     // per-step action s_n written to per_step
+};
+
+// Lennard-Jones pair constants (Eq. 16) prepared on the host.
+struct LJConst {
+  double box, inv_box;
+  double rc2;        // cutoff^2: pair included when r^2 <= rc2
+  double a24;        // 24 eps
+  double sig2;       // sigma^2
+  double duc;        // u'(r_c)
+};
+
+// One path as seen by the LJ kernels.
+struct PathArgs {
+  const double* x;        // (N+1) * 3 * n_atoms
+  const double* weights;  // N or null
+  double* grad;           // (N+1) * 3 * n_atoms or null
+  double* per_step;       // N (always provided: workspace when the caller passed null)
+  double* excess;         // N or null
+  double* bnd;            // (n_tiles - 1) * 3 * n_atoms boundary terms, or null
+  int64_t n_steps;
+  int32_t n_atoms;
+  int32_t tile;           // steps per tile
+  int32_t n_tiles;
+  int32_t mode;
+  double mu_dt;           // dt / gamma
+  double inv4Ddt;         // 1 / (4 D dt)
+  double c;               // 1 / (2 D dt)
+  LJConst lj;
+  // neighbour list geometry
+  double rlist2;          // (rc + skin)^2
+  double half_skin2;      // (skin / 2)^2: rebuild when an atom moved further
+  int32_t nc;             // cells per axis (0: all pairs)
+  int32_t reach;          // stencil half-width in cells
+  int32_t kmax;           // list capacity per atom
+  int32_t pad0;
+};
+
+// Per-block scratch in global memory for the fused LJ kernel.
+struct BlockScratch {
+  uint16_t* nbr;   // kmax * n_atoms per block
+  int32_t* cnt;    // n_atoms per block
+  double* xref;    // 6 * n_atoms per block: list-build positions, then rho_{n-1}
+  double* rglob;   // 3 * n_atoms per block (residuals when they do not fit in LDS), or null
+  int64_t nbr_stride, cnt_stride, xref_stride, rglob_stride;  // elements per block
+};
+
+struct FusedLaunch {
+  int block;        // threads per block
+  int grid;         // blocks
+  bool r_in_lds;
+  bool f32;
+  size_t lds_bytes;
+};
+
+// Batch work item: one tile of one member path.
+struct BatchItem {
+  int32_t path;
+  int32_t tile;
+};
+
+// Batch member descriptor (uploaded once): PathArgs with null pointers plus
+// element offsets into the packed buffers passed at call time.
+struct BatchMember {
+  PathArgs a;
+  int64_t x_off;      // into x_all / grad_all
+  int64_t step_off;   // into weights_all / per_step_all
+  int64_t bnd_off;    // into the workspace boundary buffer
+};
+
+// Packed buffers of one batch call.
+struct BatchBase {
+  const double* x;
+  const double* weights;
+  double* grad;
+  double* per_step;
+  double* bnd;
+  int32_t mode;
+  int32_t pad0;
+};
+
+size_t fused_lds_bytes(int n_atoms, int nc, bool r_in_lds);
+size_t plain_lds_bytes(int n_atoms, int nc);
+
+hipError_t launch_lj_fused(const PathArgs& a, const BlockScratch& s, const FusedLaunch& L,
+                           hipStream_t st);
+hipError_t launch_lj_finalize(const PathArgs& a, double* action, hipStream_t st);
+hipError_t launch_lj_batch(const BatchMember* members, const BatchBase& base,
+                           const BatchItem* items, int n_items, int* counter,
+                           const BlockScratch& s, const FusedLaunch& L, hipStream_t st);
+hipError_t launch_batch_finalize(const BatchMember* members, const BatchBase& base,
+                                 const int32_t* member_slot, int n_members, double* actions,
+                                 int max_tiles, hipStream_t st);
+hipError_t launch_reset_counter(int* counter, hipStream_t st);
+
+// Plain (unfused) LJ pipeline.
+struct PlainArgs {
+  PathArgs p;
+  uint16_t* nbr;   // N * kmax * n_atoms
+  int32_t* cnt;    // N * n_atoms
+  double* F;       // N * 3 * n_atoms
+  double* R;       // N * 3 * n_atoms (weighted residuals)
+  double* Q;       // N * 3 * n_atoms
+};
+hipError_t launch_lj_plain(const PlainArgs& a, int block, bool f32, double* action,
+                           hipStream_t st);
+
+// Harmonic path.
+struct HOArgs {
+  const double* x;
+  const double* weights;
+  double* grad;
+  double* per_step;
+  double* excess;
+  int64_t n_steps;
+  int64_t n_dof;
+  double k;
+  double mu_dt, inv4Ddt, c;
+  int32_t mode;
+  int32_t seg;     // lanes per slice in the reduction (power of two <= 64)
+};
+hipError_t launch_ho(const HOArgs& a, double* action, hipStream_t st);
+hipError_t launch_sum(const double* v, int64_t n, double* out, hipStream_t st);
+
+// Path sampling.
+struct MHArgs {
+  double* x;
+  double* trial;
+  double* excess;        // e_n of x
+  double* excess_trial;  // e'_n (workspace)
+  double* frag_delta;    // may be null
+  int32_t* frag_accept;  // may be null
+  int32_t* step_info;    // may be null
+  int32_t* state;        // workspace: {l, u, n_frag, n_acc}
+  int32_t* acc_ws;       // workspace: accept flag per fragment
+  int64_t* sweep_counter;
+  int64_t n_steps;
+  int64_t n_dof;
+  uint32_t key0, key1;
+  int32_t l_min, l_max;
+  double sig;            // sqrt(2 D dt)
+};
+hipError_t launch_mh_prepare(const MHArgs& m, hipStream_t st);
+hipError_t launch_mh_trial(const MHArgs& m, hipStream_t st);
+hipError_t launch_mh_accept(const MHArgs& m, hipStream_t st);
+
+}  // namespace pamd

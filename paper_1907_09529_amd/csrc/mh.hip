@@ -1,0 +1,216 @@
+// One Monte Carlo step of the multilevel sliding-and-sampling path move (Sec. III):
+// random level and offset, free-particle trial fragments with fixed endpoints,
+// fragment-wise Metropolis-Hastings test on the excess action, commit.
+// Random numbers: Philox4x32-10 (Salmon et al., SC'11) with the stream layout
+// documented in pamd.h; trial normals by Box-Muller.
+#include <algorithm>
+
+#include "device.hpp"
+#include "internal.hpp"
+
+namespace pamd {
+
+struct U4 {
+  uint32_t v[4];
+};
+
+// Philox4x32-10: 10 rounds of (c0,c1,c2,c3) <- (hi(M1 c2)^c1^k0, lo(M1 c2), hi(M0 c0)^c3^k1, lo(M0 c0)),
+// key bumped by the Weyl constants before every round but the first.
+__device__ __forceinline__ U4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                     uint32_t k0, uint32_t k1) {
+  const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r > 0) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    const uint32_t hi0 = __umulhi(M0, c0), lo0 = M0 * c0;
+    const uint32_t hi1 = __umulhi(M1, c2), lo1 = M1 * c2;
+    const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+    c0 = n0;
+    c1 = lo1;
+    c2 = n2;
+    c3 = lo0;
+  }
+  U4 o;
+  o.v[0] = c0;
+  o.v[1] = c1;
+  o.v[2] = c2;
+  o.v[3] = c3;
+  return o;
+}
+
+// Exact double in (0, 1): ((a >> 6) 2^26 + (b >> 6) + 1/2) 2^-52.
+__device__ __forceinline__ double uniform52(uint32_t a, uint32_t b) {
+  const double k = (double)(a >> 6) * 67108864.0 + (double)(b >> 6);
+  return (k + 0.5) * (1.0 / 4503599627370496.0);
+}
+
+__device__ __forceinline__ double trial_normal(uint64_t e, uint32_t sweep, uint32_t k0,
+                                               uint32_t k1) {
+  const uint64_t p = e >> 1;
+  const U4 w = philox((uint32_t)p, (uint32_t)(p >> 32), sweep, 3u, k0, k1);
+  const double u1 = uniform52(w.v[0], w.v[1]);
+  const double u2 = uniform52(w.v[2], w.v[3]);
+  const double rad = sqrt(-2.0 * log(u1));
+  double sn, cs;
+  sincos(2.0 * M_PI * u2, &sn, &cs);
+  return rad * ((e & 1) ? sn : cs);
+}
+
+__global__ void mh_prepare_kernel(MHArgs m) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const uint32_t s = (uint32_t)(*m.sweep_counter);
+  const U4 w = philox(0u, 0u, s, 1u, m.key0, m.key1);
+  const int l = m.l_min + (int)(w.v[0] % (uint32_t)(m.l_max - m.l_min + 1));
+  const int64_t span = (int64_t)1 << l;
+  const int64_t u = 1 + (int64_t)(w.v[1] % (uint32_t)span);
+  const int64_t n_end = (m.n_steps - u) / span + 1;           // endpoints u + k span <= N
+  const int64_t last = u + (n_end - 1) * span;
+  const int64_t n_frag = n_end + (last < m.n_steps ? 1 : 0);
+  m.state[0] = l;
+  m.state[1] = (int32_t)u;
+  m.state[2] = (int32_t)n_frag;
+  m.state[3] = 0;
+}
+
+// Fragment f spans [a, b]; f = 0 is the tail [0, u]; the nose (if any) ends at N.
+__device__ __forceinline__ void frag_range(int f, int l, int64_t u, int n_frag, int64_t N,
+                                           int64_t& a, int64_t& b, bool& nose) {
+  const int64_t span = (int64_t)1 << l;
+  if (f == 0) {
+    a = 0;
+    b = u;
+  } else {
+    a = u + (int64_t)(f - 1) * span;
+    b = std::min(a + span, N);
+  }
+  nose = (f == n_frag - 1) && (b == N) && ((N - u) % span != 0);
+}
+
+__global__ void mh_trial_kernel(MHArgs m) {
+  const int l = m.state[0];
+  const int64_t u = m.state[1];
+  const int n_frag = m.state[2];
+  const uint32_t s = (uint32_t)(*m.sweep_counter);
+  const int64_t total = (int64_t)n_frag * m.n_dof;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int f = (int)(t / m.n_dof);
+    const int64_t e = t - (int64_t)f * m.n_dof;
+    int64_t a, b;
+    bool nose;
+    frag_range(f, l, u, n_frag, m.n_steps, a, b, nose);
+    double y = m.x[a * m.n_dof + e];
+    m.trial[a * m.n_dof + e] = y;
+    if (nose) {
+      for (int64_t k = a; k < b; ++k) {
+        y = fma(m.sig, trial_normal((uint64_t)(k + 1) * m.n_dof + e, s, m.key0, m.key1), y);
+        m.trial[(k + 1) * m.n_dof + e] = y;
+      }
+    } else {
+      const double xb = m.x[b * m.n_dof + e];
+      for (int64_t k = a; k < b - 1; ++k) {
+        const double rem = (double)(b - k);
+        const double z = trial_normal((uint64_t)(k + 1) * m.n_dof + e, s, m.key0, m.key1);
+        y = y + (xb - y) / rem + m.sig * sqrt((rem - 1.0) / rem) * z;
+        m.trial[(k + 1) * m.n_dof + e] = y;
+      }
+      if (b == m.n_steps) m.trial[b * m.n_dof + e] = xb;
+    }
+  }
+}
+
+__global__ void mh_accept_kernel(MHArgs m) {
+  __shared__ double red[32];
+  const int l = m.state[0];
+  const int64_t u = m.state[1];
+  const int n_frag = m.state[2];
+  const uint32_t s = (uint32_t)(*m.sweep_counter);
+  double n_acc = 0.0;
+  for (int f = threadIdx.x; f < n_frag; f += blockDim.x) {
+    int64_t a, b;
+    bool nose;
+    frag_range(f, l, u, n_frag, m.n_steps, a, b, nose);
+    double delta = 0.0;
+    for (int64_t n = a; n < b; ++n) delta += m.excess_trial[n] - m.excess[n];
+    const U4 w = philox((uint32_t)f, 0u, s, 2u, m.key0, m.key1);
+    const double uf = uniform52(w.v[0], w.v[1]);
+    const int acc = (uf < exp(-delta)) ? 1 : 0;
+    m.acc_ws[f] = acc;
+    if (m.frag_delta) m.frag_delta[f] = delta;
+    if (m.frag_accept) m.frag_accept[f] = acc;
+    n_acc += acc;
+  }
+  const double tot = block_sum(n_acc, red);
+  if (threadIdx.x == 0) {
+    m.state[3] = (int)tot;
+    if (m.step_info) {
+      m.step_info[0] = l;
+      m.step_info[1] = (int32_t)u;
+      m.step_info[2] = n_frag;
+      m.step_info[3] = (int)tot;
+    }
+  }
+}
+
+// Copies accepted fragments into x and their excess actions into `excess`,
+// then advances the sweep counter.
+__global__ void mh_commit_kernel(MHArgs m) {
+  const int l = m.state[0];
+  const int64_t u = m.state[1];
+  const int64_t total = (m.n_steps + 1) * m.n_dof;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t n = t / m.n_dof;
+    if (n == 0) continue;
+    bool endpoint = false;
+    int f;
+    if (n < u) {
+      f = 0;
+    } else {
+      const int64_t k = n - u;
+      endpoint = (k & (((int64_t)1 << l) - 1)) == 0;
+      f = 1 + (int)(k >> l);
+    }
+    if (!endpoint && m.acc_ws[f]) m.x[t] = m.trial[t];
+  }
+  for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < m.n_steps;
+       n += (int64_t)gridDim.x * blockDim.x) {
+    const int f = (n < u) ? 0 : 1 + (int)((n - u) >> l);
+    if (m.acc_ws[f]) m.excess[n] = m.excess_trial[n];
+  }
+}
+
+__global__ void mh_advance_kernel(MHArgs m) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *m.sweep_counter += 1;
+}
+
+hipError_t launch_mh_prepare(const MHArgs& m, hipStream_t st) {
+  hipLaunchKernelGGL(mh_prepare_kernel, dim3(1), dim3(64), 0, st, m);
+  return hipGetLastError();
+}
+
+hipError_t launch_mh_trial(const MHArgs& m, hipStream_t st) {
+  const int64_t max_frag = m.n_steps / ((int64_t)1 << m.l_min) + 2;
+  const int64_t total = max_frag * m.n_dof;
+  const int64_t blocks = std::min<int64_t>((total + 255) / 256, 16384);
+  hipLaunchKernelGGL(mh_trial_kernel, dim3((unsigned)blocks), dim3(256), 0, st, m);
+  return hipGetLastError();
+}
+
+hipError_t launch_mh_accept(const MHArgs& m, hipStream_t st) {
+  hipLaunchKernelGGL(mh_accept_kernel, dim3(1), dim3(1024), 0, st, m);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int64_t total = (m.n_steps + 1) * m.n_dof;
+  const int64_t blocks = std::min<int64_t>((total + 255) / 256, 16384);
+  hipLaunchKernelGGL(mh_commit_kernel, dim3((unsigned)blocks), dim3(256), 0, st, m);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(mh_advance_kernel, dim3(1), dim3(64), 0, st, m);
+  return hipGetLastError();
+}
+
+}  // namespace pamd

@@ -1,0 +1,198 @@
+"""Host-side checks of the C ABI (no GPU needed).
+
+The library validates every argument before any device work, so error
+returns can be exercised on a machine without a GPU.  Device pointers here are
+fake non-null addresses that are never dereferenced.
+"""
+import ctypes
+import math
+import os
+import re
+
+import pytest
+
+import paper_1907_09529_amd as P
+from paper_1907_09529_amd import _lib
+from oracle import action as OA
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pamd.h")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(_lib.LIB_PATH),
+                                reason="libpamd.so not built (run __graft_entry__.build())")
+
+FAKE = ctypes.c_void_p(0x100000)        # aligned, never dereferenced
+FAKE_BAD = ctypes.c_void_p(0x100010)    # not 256-byte aligned
+BOX864 = (864 / 0.8442) ** (1 / 3)
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(pamd_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_exports_every_declared_symbol():
+    lib = P.load()
+    names = declared_functions()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(_lib.EXPORTED)
+
+
+def lj_path(**kw):
+    d = dict(n_steps=64, n_atoms=864, n_dim=3, dt=1e-4, D=1.0, gamma=1.0)
+    d.update(kw)
+    return P.make_path(**d)
+
+
+def lj_pot(**kw):
+    d = dict(eps=1.0, sigma=1.0, rc=2.5, box=BOX864)
+    d.update(kw)
+    return P.make_potential("lj", **d)
+
+
+def ws_size(path, pot, tuning=None):
+    n = ctypes.c_size_t(0)
+    code = P.load().pamd_workspace_size(ctypes.byref(path), ctypes.byref(pot),
+                                        ctypes.byref(tuning) if tuning else None, ctypes.byref(n))
+    return code, n.value
+
+
+def action_call(path, pot, x=FAKE, action=FAKE, ws=FAKE, ws_bytes=None, tuning=None):
+    if ws_bytes is None:
+        ws_bytes = ws_size(path, pot, tuning)[1]
+    return P.load().pamd_action(ctypes.byref(path), ctypes.byref(pot),
+                                ctypes.byref(tuning) if tuning else None, x, action, None, ws,
+                                ctypes.c_size_t(ws_bytes), None)
+
+
+@pytest.mark.parametrize("bad,code", [
+    (dict(n_steps=0), _lib.PAMD_EINVAL),
+    (dict(n_atoms=0), _lib.PAMD_EINVAL),
+    (dict(n_dim=2), _lib.PAMD_EUNSUPPORTED),
+    (dict(n_dim=1), _lib.PAMD_EUNSUPPORTED),     # LJ needs 3 dimensions
+    (dict(dt=0.0), _lib.PAMD_EINVAL),
+    (dict(dt=float("nan")), _lib.PAMD_EINVAL),
+    (dict(D=-1.0), _lib.PAMD_EINVAL),
+    (dict(gamma=0.0), _lib.PAMD_EINVAL),
+    (dict(n_atoms=70000), _lib.PAMD_EUNSUPPORTED),
+])
+def test_path_validation(bad, code):
+    c, _ = ws_size(lj_path(**bad), lj_pot())
+    assert c == code
+    assert P.load().pamd_last_error()
+
+
+def test_precision_validation():
+    p = lj_path()
+    p.precision = 7
+    assert ws_size(p, lj_pot())[0] == _lib.PAMD_EINVAL
+
+
+@pytest.mark.parametrize("bad,code", [
+    (dict(rc=6.0), _lib.PAMD_EUNSUPPORTED),      # r_c > L/2
+    (dict(box=0.0), _lib.PAMD_EINVAL),
+    (dict(eps=0.0), _lib.PAMD_EINVAL),
+    (dict(sigma=-1.0), _lib.PAMD_EINVAL),
+    (dict(rc=float("inf")), _lib.PAMD_EINVAL),
+])
+def test_potential_validation(bad, code):
+    assert ws_size(lj_path(), lj_pot(**bad))[0] == code
+
+
+def test_harmonic_rejects_box_and_unknown_kind():
+    p = P.make_path(16, 1, 1, 0.01, 1.0, 1.0)
+    h = P.make_potential("harmonic")
+    h.box = 3.0
+    assert ws_size(p, h)[0] == _lib.PAMD_EUNSUPPORTED
+    h.box = 0.0
+    h.kind = 9
+    assert ws_size(p, h)[0] == _lib.PAMD_EINVAL
+
+
+@pytest.mark.parametrize("field,value", [("algo", 5), ("block", 100), ("block", 2048),
+                                         ("tile", -1), ("max_neighbours", -3)])
+def test_tuning_validation(field, value):
+    t = P.make_tuning()
+    setattr(t, field, value)
+    assert ws_size(lj_path(), lj_pot(), t)[0] == _lib.PAMD_EINVAL
+
+
+def test_null_pointers_and_workspace():
+    path, pot = lj_path(), lj_pot()
+    assert action_call(path, pot, x=None) == _lib.PAMD_EINVAL
+    assert action_call(path, pot, action=None) == _lib.PAMD_EINVAL
+    need = ws_size(path, pot)[1]
+    assert need > 0
+    assert action_call(path, pot, ws_bytes=need - 1) == _lib.PAMD_EWORKSPACE
+    assert action_call(path, pot, ws=FAKE_BAD) == _lib.PAMD_EWORKSPACE
+    assert action_call(path, pot, ws=None) == _lib.PAMD_EINVAL
+    lib = P.load()
+    code = lib.pamd_action_grad(ctypes.byref(path), ctypes.byref(pot), None, FAKE, None, None,
+                                None, None, FAKE, ctypes.c_size_t(need), None)
+    assert code == _lib.PAMD_EINVAL and b"grad" in lib.pamd_last_error()
+    code = lib.pamd_excess_action(ctypes.byref(path), ctypes.byref(pot), None, FAKE, None, None,
+                                  FAKE, ctypes.c_size_t(need), None)
+    assert code == _lib.PAMD_EINVAL
+
+
+def test_workspace_grows_with_problem_and_plain_form():
+    small = ws_size(lj_path(n_steps=64), lj_pot())[1]
+    big = ws_size(lj_path(n_steps=4096), lj_pot())[1]
+    plain = ws_size(lj_path(n_steps=4096), lj_pot(), P.make_tuning("plain"))[1]
+    assert 0 < small < big < plain
+    assert big % 256 == 0
+
+
+def test_mh_validation():
+    path, pot = lj_path(n_steps=64), lj_pot()
+    lib = P.load()
+    n = ctypes.c_size_t(0)
+    assert lib.pamd_mh_workspace_size(ctypes.byref(path), ctypes.byref(pot), None,
+                                      ctypes.byref(n)) == 0
+
+    def step(l_min, l_max, counter=FAKE):
+        return lib.pamd_mh_step(ctypes.byref(path), ctypes.byref(pot), None, 1, l_min, l_max,
+                                counter, FAKE, FAKE, FAKE, None, None, None, FAKE,
+                                ctypes.c_size_t(n.value), None)
+
+    assert step(0, 2) == _lib.PAMD_EINVAL
+    assert step(3, 2) == _lib.PAMD_EINVAL
+    assert step(2, 7) == _lib.PAMD_EINVAL          # 2^7 > 64 steps
+    assert step(2, 3, counter=None) == _lib.PAMD_EINVAL
+
+
+def test_batch_validation_and_layout():
+    paths = [lj_path(n_steps=100, n_atoms=108, ), lj_path(n_steps=37, n_atoms=256),
+             P.make_path(50, 4, 3, 0.01, 1.0, 1.0)]
+    paths[0].n_atoms = 108
+    pots = [lj_pot(box=(108 / 0.8442) ** (1 / 3)), lj_pot(box=(256 / 0.8442) ** (1 / 3)),
+            P.make_potential("harmonic")]
+    b = P.PamdBatch(paths, pots)
+    assert b.x_offsets[0] == 0
+    for p in range(3):
+        n = (paths[p].n_steps + 1) * paths[p].n_dim * paths[p].n_atoms
+        assert b.x_offsets[p + 1] - b.x_offsets[p] >= n
+        assert b.x_offsets[p] % 32 == 0
+    assert b.ws_bytes > 0
+    b.close()
+    bad = [lj_path(n_steps=10, n_atoms=108)]
+    bad[0].precision = 1
+    with pytest.raises(P.PamdError):
+        P.PamdBatch(bad + [lj_path(n_steps=10, n_atoms=108)], [pots[0], pots[0]])
+    with pytest.raises(P.PamdError):
+        P.PamdBatch([lj_path()], [lj_pot(rc=9.0)])
+
+
+def test_log_norm_matches_oracle():
+    path = lj_path(n_steps=4096)
+    ref = OA.log_norm(4096, 3, 864, 1.0, 1e-4)
+    assert abs(P.pamd_log_norm(path) - ref) <= 1e-12 * abs(ref)
+    bad = lj_path(n_steps=0)
+    assert math.isnan(P.pamd_log_norm(bad))
+
+
+def test_graph_begin_rejects_null_stream():
+    assert P.load().pamd_graph_begin(None) == _lib.PAMD_EINVAL

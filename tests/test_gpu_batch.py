@@ -1,0 +1,81 @@
+"""GPU parity of the persistent batched launch against the oracle and single-path calls."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import paper_1907_09529_amd as P
+import workloads as W
+from oracle import action as OA
+
+from common import em_input, lib_descriptors, oracle_full, oracle_pot, rel, rel_inf
+
+pytestmark = pytest.mark.gpu
+
+
+def pack(batch, arrays):
+    total = batch.x_offsets[-1]
+    buf = np.zeros(total)
+    for p, X in enumerate(arrays):
+        o = batch.x_offsets[p]
+        buf[o:o + X.size] = X.ravel()
+    return torch.from_numpy(buf).cuda()
+
+
+def test_small_mixed_batch_vs_oracle(device):
+    members = [em_input("lj108", n_steps=40), em_input("lj27", n_steps=21),
+               em_input("lj108", n_atoms=256, n_steps=13), em_input("ho1d", n_steps=50),
+               em_input("lj108", n_steps=1)]
+    paths, pots = zip(*(lib_descriptors(w) for w, _ in members))
+    b = P.PamdBatch(list(paths), list(pots))
+    x = pack(b, [X for _, X in members])
+    grad = torch.zeros_like(x)
+    act = torch.empty(len(members), dtype=torch.float64, device="cuda")
+    ps = torch.empty(b.step_offsets[-1], dtype=torch.float64, device="cuda")
+    b.pamd_batch_action_grad(x, act, grad_all=grad, per_step_all=ps)
+    torch.cuda.synchronize()
+    for p, (w, X) in enumerate(members):
+        s_ref, g_ref = oracle_full(w, X)
+        assert rel(float(act[p]), math.fsum(s_ref.tolist())) <= 1e-12, p
+        assert np.max(np.abs(b.steps_view(ps, p).cpu().numpy() - s_ref) / s_ref) <= 1e-12, p
+        assert rel_inf(b.view(grad, p).cpu().numpy(), g_ref) <= 1e-10, p
+    # repeated calls reuse the prepared workspace and give identical results
+    act2 = torch.empty_like(act)
+    b.pamd_batch_action_grad(x, act2)
+    torch.cuda.synchronize()
+    assert torch.equal(act, act2)
+
+
+def test_batch64_full_workload(device):
+    """The 64-path workload: every member against the single-path call, sampled
+    slices of three members against the oracle."""
+    ws = W.batch_members()
+    paths, pots, arrays = [], [], []
+    for w in ws:
+        X = W.tethered_path(w)
+        arrays.append(X)
+        pa, po = lib_descriptors(w)
+        paths.append(pa)
+        pots.append(po)
+    b = P.PamdBatch(paths, pots)
+    x = pack(b, arrays)
+    grad = torch.zeros_like(x)
+    act = torch.empty(len(ws), dtype=torch.float64, device="cuda")
+    b.pamd_batch_action_grad(x, act, grad_all=grad)
+    torch.cuda.synchronize()
+    for p, w in enumerate(ws):
+        g1 = torch.empty_like(b.view(x, p))
+        a1 = torch.empty(1, dtype=torch.float64, device="cuda")
+        P.pamd_action_grad(paths[p], pots[p], b.view(x, p).contiguous(), g1, action=a1)
+        torch.cuda.synchronize()
+        assert rel(float(act[p]), float(a1)) <= 1e-12, p
+        assert rel_inf(b.view(grad, p).cpu().numpy(), g1.cpu().numpy()) <= 1e-10, p
+    rng = np.random.default_rng(0)
+    for p in rng.choice(len(ws), size=3, replace=False):
+        w, X = ws[p], arrays[p]
+        pot = oracle_pot(w)
+        gp = b.view(grad, int(p)).cpu().numpy()
+        for m in sorted({0, int(rng.integers(1, w.n_steps)), w.n_steps}):
+            _, gm = OA.slice_terms(X, m, pot, w.dt, w.D, w.gamma)
+            assert rel_inf(gp[m], gm) <= 1e-10, (p, m)

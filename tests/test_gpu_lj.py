@@ -1,0 +1,247 @@
+"""GPU parity of the Lennard-Jones path action and adjoint gradient against the oracle.
+
+Tolerances (FP64 path): action and every per-step term within 1e-12 relative;
+gradient within 1e-10 in the normwise sense ||g - g_ref||_inf / ||g_ref||_inf.
+FP32-force variant: gradient within 1e-8; its action error is printed.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import paper_1907_09529_amd as P
+import workloads as W
+from oracle import action as OA
+from oracle import sampling as OS
+
+from common import em_input, lib_descriptors, oracle_full, oracle_pot, rel, rel_inf
+
+pytestmark = pytest.mark.gpu
+
+ACTION_TOL = 1e-12
+GRAD_TOL = 1e-10
+GRAD_TOL_F32 = 1e-8
+
+
+def run(w, X, precision="fp64", tuning=None, weights=None):
+    path, pot = lib_descriptors(w, precision)
+    x = torch.from_numpy(np.ascontiguousarray(X)).cuda()
+    grad = torch.empty_like(x)
+    act = torch.empty(1, dtype=torch.float64, device="cuda")
+    per_step = torch.empty(w.n_steps, dtype=torch.float64, device="cuda")
+    wt = None if weights is None else torch.from_numpy(np.asarray(weights, dtype=np.float64)).cuda()
+    P.pamd_action_grad(path, pot, x, grad, action=act, per_step=per_step, step_weights=wt,
+                       tuning=tuning)
+    torch.cuda.synchronize()
+    return float(act.item()), per_step.cpu().numpy(), grad.cpu().numpy()
+
+
+def check(w, X, tuning=None, precision="fp64", weights=None, ref=None):
+    s_ref, g_ref = ref if ref is not None else oracle_full(w, X, weights)
+    S, s, g = run(w, X, precision, tuning, weights)
+    S_ref = math.fsum(s_ref.tolist())
+    gtol = GRAD_TOL if precision == "fp64" else GRAD_TOL_F32
+    err_s = rel(S, S_ref)
+    err_g = rel_inf(g, g_ref)
+    if precision == "fp64":
+        assert err_s <= ACTION_TOL, err_s
+        assert np.max(np.abs(s - s_ref) / np.abs(s_ref)) <= ACTION_TOL
+    else:
+        print(f"FP32-force action relative error vs FP64 oracle: {err_s:.3e}")
+        assert err_s <= 1e-8
+    assert err_g <= gtol, err_g
+    return err_s, err_g
+
+
+@pytest.fixture(scope="module")
+def lj108():
+    return em_input("lj108")
+
+
+@pytest.fixture(scope="module")
+def lj108_ref(lj108):
+    w, X = lj108
+    return oracle_full(w, X)
+
+
+def test_lj108_fused_fp64(device, lj108, lj108_ref):
+    w, X = lj108
+    check(w, X, ref=lj108_ref)
+
+
+def test_lj108_plain_fp64(device, lj108, lj108_ref):
+    w, X = lj108
+    check(w, X, tuning=P.make_tuning("plain"), ref=lj108_ref)
+
+
+def test_lj108_fp32_force(device, lj108, lj108_ref):
+    w, X = lj108
+    e_s, e_g = check(w, X, precision="fp32_force", ref=lj108_ref)
+    print(f"lj108 FP32-force: action rel {e_s:.2e}, grad rel {e_g:.2e}")
+
+
+def test_lj108_fp32_force_plain(device, lj108, lj108_ref):
+    w, X = lj108
+    check(w, X, precision="fp32_force", tuning=P.make_tuning("plain"), ref=lj108_ref)
+
+
+@pytest.mark.parametrize("tile,skin,kmax", [(1, 0.3, 0), (7, 0.3, 0), (16, 1e-6, 0),
+                                            (32, 0.9, 0), (5, 0.3, 4), (300, 0.3, 0)])
+def test_lj108_tiles_skins_overflow(device, lj108, lj108_ref, tile, skin, kmax):
+    w, X = lj108
+    check(w, X, tuning=P.make_tuning("fused", tile=tile, skin=skin, max_neighbours=kmax),
+          ref=lj108_ref)
+
+
+@pytest.mark.parametrize("block", [64, 128, 192, 1024])
+def test_lj108_block_sizes(device, lj108, lj108_ref, block):
+    w, X = lj108
+    check(w, X, tuning=P.make_tuning("fused", block=block), ref=lj108_ref)
+
+
+def test_lj108_step_weights(device, lj108):
+    w, X = lj108
+    wts = np.random.default_rng(5).uniform(-1.0, 2.0, size=w.n_steps)
+    check(w, X, weights=wts)
+    check(w, X, weights=wts, tuning=P.make_tuning("plain"))
+
+
+def test_lj108_excess_action(device, lj108, lj108_ref):
+    w, X = lj108
+    path, pot = lib_descriptors(w)
+    x = torch.from_numpy(np.ascontiguousarray(X)).cuda()
+    ex = torch.empty(w.n_steps, dtype=torch.float64, device="cuda")
+    ps = torch.empty_like(ex)
+    for tun in (None, P.make_tuning("plain")):
+        P.pamd_excess_action(path, pot, x, ex, per_step=ps, tuning=tun)
+        torch.cuda.synchronize()
+        s0 = OS.free_step_action(X, w.D, w.dt, w.box)
+        ref = lj108_ref[0] - s0
+        # e_n is small against s_n: compare against the scale of s_n
+        assert np.max(np.abs(ex.cpu().numpy() - ref)) <= 1e-11 * np.max(np.abs(lj108_ref[0]))
+        assert np.max(np.abs(ps.cpu().numpy() - lj108_ref[0]) / lj108_ref[0]) <= ACTION_TOL
+
+
+def test_lj108_action_only_matches(device, lj108, lj108_ref):
+    w, X = lj108
+    path, pot = lib_descriptors(w)
+    x = torch.from_numpy(np.ascontiguousarray(X)).cuda()
+    act = torch.empty(1, dtype=torch.float64, device="cuda")
+    ps = torch.empty(w.n_steps, dtype=torch.float64, device="cuda")
+    P.pamd_action(path, pot, x, act, per_step=ps)
+    torch.cuda.synchronize()
+    assert rel(float(act.item()), math.fsum(lj108_ref[0].tolist())) <= ACTION_TOL
+
+
+def test_bitwise_repeatable(device, lj108):
+    w, X = lj108
+    a1 = run(w, X)
+    a2 = run(w, X)
+    assert a1[0] == a2[0]
+    assert np.array_equal(a1[1], a2[1]) and np.array_equal(a1[2], a2[2])
+
+
+def test_paper_lj27_state_point(device):
+    w, X = em_input("lj27")
+    check(w, X)
+    check(w, X, tuning=P.make_tuning("plain"))
+
+
+def test_single_step_and_short_paths(device):
+    for n in (1, 2, 3):
+        w, X = em_input("lj108", n_steps=n)
+        check(w, X)
+        check(w, X, tuning=P.make_tuning("plain"))
+
+
+def test_lj864_em_ragged_tiles(device):
+    w, X = em_input("lj864", n_steps=40)
+    ref = oracle_full(w, X)
+    check(w, X, ref=ref)
+    check(w, X, tuning=P.make_tuning("fused", tile=7), ref=ref)
+    check(w, X, tuning=P.make_tuning("plain"), ref=ref)
+    check(w, X, precision="fp32_force", ref=ref)
+
+
+def test_lj500_cell_list_path(device):
+    # 500 atoms: n_c = 3 cells of edge >= 2.8 (reach 1) or 5 with reach 2
+    w, X = em_input("lj108", n_atoms=500, n_steps=24)
+    ref = oracle_full(w, X)
+    check(w, X, ref=ref)
+    check(w, X, tuning=P.make_tuning("fused", skin=0.05), ref=ref)
+    check(w, X, tuning=P.make_tuning("plain"), ref=ref)
+
+
+# ---------------------------------------------------------------------------
+# Full-size headline workload (864 atoms x 4096 steps), default launch shape.
+# The oracle checks sampled slices one by one; the rest is checked through
+# properties that hold at any size.
+# ---------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def lj864_full():
+    w = W.workload("lj864")
+    X = W.tethered_path(w)
+    return w, X
+
+
+def _sample_slices(w, tile):
+    rng = np.random.default_rng(w.seed + 11)
+    picks = {0, 1, w.n_steps - 1, w.n_steps, tile - 1, tile, tile + 1, 2 * tile,
+             w.n_steps - tile, w.n_steps - tile + 1}
+    picks |= set(int(v) for v in rng.integers(0, w.n_steps + 1, size=6))
+    return sorted(p for p in picks if 0 <= p <= w.n_steps)
+
+
+def test_lj864_full_size_sampled(device, lj864_full):
+    w, X = lj864_full
+    S, s, g = run(w, X)
+    assert np.all(s > 0) and np.all(np.isfinite(g))
+    assert rel(S, math.fsum(s.tolist())) <= 1e-13
+    pot = oracle_pot(w)
+    tile = max(1, min(32, w.n_steps // 512))
+    for m in _sample_slices(w, tile):
+        sm, gm = OA.slice_terms(X, m, pot, w.dt, w.D, w.gamma)
+        assert rel_inf(g[m], gm) <= GRAD_TOL, m
+        if sm is not None:
+            assert rel(s[m], sm) <= ACTION_TOL, m
+
+
+def test_lj864_full_size_fused_equals_plain(device, lj864_full):
+    w, X = lj864_full
+    S1, s1, g1 = run(w, X)
+    S2, s2, g2 = run(w, X, tuning=P.make_tuning("plain"))
+    assert rel(S1, S2) <= ACTION_TOL
+    assert rel_inf(g1, g2) <= GRAD_TOL
+    S3, s3, g3 = run(w, X, precision="fp32_force")
+    e_s, e_g = rel(S3, S1), rel_inf(g3, g1)
+    print(f"lj864 full FP32-force vs FP64: action rel {e_s:.2e}, grad rel {e_g:.2e}")
+    assert e_g <= GRAD_TOL_F32
+
+
+def test_lj864_fd_gradient_16_coordinates(device, lj864_full):
+    """Central differences of the local action s_{m-1} + s_m (library-evaluated on
+    the 3-slice sub-path) against the adjoint gradient at 16 random coordinates."""
+    w, X = lj864_full
+    _, _, g = run(w, X)
+    rng = np.random.default_rng(w.seed + 1)
+    h = 1e-6
+    for _ in range(16):
+        m = int(rng.integers(0, w.n_steps + 1))
+        c = int(rng.integers(0, 3))
+        a = int(rng.integers(0, w.n_atoms))
+        lo, hi = max(0, m - 1), min(w.n_steps, m + 1)
+        sub = np.ascontiguousarray(X[lo:hi + 1]).copy()
+        vals = []
+        for sgn in (+1, -1):
+            Y = sub.copy()
+            Y[m - lo, c, a] += sgn * h
+            ws = w.with_steps(hi - lo)
+            path, pot = lib_descriptors(ws)
+            act = torch.empty(1, dtype=torch.float64, device="cuda")
+            P.pamd_action(path, pot, torch.from_numpy(Y).cuda(), act)
+            torch.cuda.synchronize()
+            vals.append(float(act.item()))
+        fd = (vals[0] - vals[1]) / (2 * h)
+        scale = max(abs(g[m, c, a]), 1e-3 * np.max(np.abs(g[m])))
+        assert abs(fd - g[m, c, a]) <= 2e-5 * scale + 1e-6 * np.max(np.abs(g[m])), (m, c, a)
