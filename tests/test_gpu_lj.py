@@ -2,7 +2,13 @@
 
 Tolerances (FP64 path): action and every per-step term within 1e-12 relative;
 gradient within 1e-10 in the normwise sense ||g - g_ref||_inf / ||g_ref||_inf.
-FP32-force variant: gradient within 1e-8; its action error is printed.
+
+FP32-force variant: float32 pair functions carry a relative error of a few
+float32 ulps that the 12th power of sigma/r amplifies about twelve-fold
+(~1e-6 per pair term); the gradient sees it through
+c (dt/gamma) dF = dF / 2 and through the float32 Hessian terms.  For these
+workloads that bounds the normwise gradient error near 1e-6, so the test
+holds it to 2e-6 and the action to 1e-8, and prints both measured errors.
 """
 import math
 
@@ -21,7 +27,7 @@ pytestmark = pytest.mark.gpu
 
 ACTION_TOL = 1e-12
 GRAD_TOL = 1e-10
-GRAD_TOL_F32 = 1e-8
+GRAD_TOL_F32 = 2e-6
 
 
 def run(w, X, precision="fp64", tuning=None, weights=None):
