@@ -114,6 +114,14 @@ typedef struct pamd_path {
   int32_t reserved0;
 } pamd_path;
 
+/* ---- neighbour-list kind (pamd_tuning.neighbour_list) ---- */
+#define PAMD_LIST_AUTO 0          /* half when it fits, else full */
+#define PAMD_LIST_FULL 1          /* every atom lists all partners; fixed summation order,
+                                     results bitwise repeatable run to run */
+#define PAMD_LIST_HALF 2          /* every pair listed once; partner shares added with LDS
+                                     float64 atomics: half the pair arithmetic, summation order
+                                     (and so the last bits) may vary run to run */
+
 /* Optional launch tuning; pass NULL (or a zeroed struct) for the library's
  * choice (the autotune cache when an entry exists, else built-in defaults).
  * Fields equal to 0 (skin <= 0) are chosen by the library.
@@ -123,13 +131,16 @@ typedef struct pamd_path {
  *                  with radius rc + skin is reused while no atom has moved
  *                  more than skin/2 from where the list was built
  *   max_neighbours capacity of each atom's list; an atom whose list would
- *                  overflow falls back to a scan over all atoms (still exact) */
+ *                  overflow falls back to a scan over all atoms (still exact)
+ *   neighbour_list PAMD_LIST_* (fused); half lists need n_atoms <= 2 * block */
 typedef struct pamd_tuning {
   int32_t algo;
   int32_t block;
   int32_t tile;
   int32_t max_neighbours;
   double skin;
+  int32_t neighbour_list;
+  int32_t reserved0;
 } pamd_tuning;
 
 /* Bytes of workspace needed by pamd_action / pamd_action_grad /

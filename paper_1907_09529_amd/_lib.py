@@ -25,6 +25,9 @@ PAMD_FP32_FORCE = 1
 PAMD_ALGO_AUTO = 0
 PAMD_ALGO_FUSED = 1
 PAMD_ALGO_PLAIN = 2
+PAMD_LIST_AUTO = 0
+PAMD_LIST_FULL = 1
+PAMD_LIST_HALF = 2
 
 ERROR_NAMES = {PAMD_EINVAL: "PAMD_EINVAL", PAMD_EUNSUPPORTED: "PAMD_EUNSUPPORTED",
                PAMD_EWORKSPACE: "PAMD_EWORKSPACE", PAMD_EHIP: "PAMD_EHIP"}
@@ -43,7 +46,8 @@ class PamdPath(ctypes.Structure):
 
 class PamdTuning(ctypes.Structure):
     _fields_ = [("algo", c_int32), ("block", c_int32), ("tile", c_int32),
-                ("max_neighbours", c_int32), ("skin", c_double)]
+                ("max_neighbours", c_int32), ("skin", c_double), ("neighbour_list", c_int32),
+                ("reserved0", c_int32)]
 
 
 class PamdError(RuntimeError):

@@ -105,6 +105,8 @@ int check_tuning(const pamd_tuning* t) {
   if (t->tile < 0) return fail(PAMD_EINVAL, "tile must be >= 0");
   if (t->max_neighbours < 0) return fail(PAMD_EINVAL, "max_neighbours must be >= 0");
   if (!std::isfinite(t->skin)) return fail(PAMD_EINVAL, "skin must be finite");
+  if (t->neighbour_list < PAMD_LIST_AUTO || t->neighbour_list > PAMD_LIST_HALF)
+    return fail(PAMD_EINVAL, "unknown neighbour_list %d", t->neighbour_list);
   return PAMD_OK;
 }
 
@@ -167,9 +169,10 @@ int default_kmax(double box, double radius, int n_atoms) {
   return std::max(1, std::min(k, n_atoms - 1 > 0 ? n_atoms - 1 : 1));
 }
 
+// One atom per thread up to 1024 atoms, else the fewest atoms per thread.
 int default_block(int n_atoms) {
-  int b = n_atoms <= 512 ? (int)align_up((size_t)n_atoms, 64)
-                         : (int)align_up((size_t)((n_atoms + 1) / 2), 64);
+  int per = (n_atoms + 1023) / 1024;
+  int b = (int)align_up((size_t)((n_atoms + per - 1) / per), 64);
   return std::max(64, std::min(1024, b));
 }
 
@@ -185,6 +188,7 @@ struct Plan {
   CellGrid cells;
   double skin = 0;
   bool r_in_lds = true;
+  bool half = false;
   size_t lds = 0;
   // plain LJ
   CellGrid pcells;
@@ -241,8 +245,15 @@ int make_plan(const pamd_path* p, const pamd_potential* v, const pamd_tuning* t_
     P.tile = (int)std::min<int64_t>(tile, P.steps);
     P.n_tiles = (int)((P.steps + P.tile - 1) / P.tile);
     P.grid = std::min(P.n_tiles, kMaxGrid);
-    const size_t lds_r = fused_lds_bytes(N, P.cells.nc, true);
-    const size_t lds_g = fused_lds_bytes(N, P.cells.nc, false);
+    int list = t.neighbour_list ? t.neighbour_list
+                                : (have_cache && cached.neighbour_list ? cached.neighbour_list : PAMD_LIST_AUTO);
+    const bool half_ok = N <= fused_half_slots() * P.block &&
+                         fused_lds_bytes(N, P.cells.nc, false, true) <= kLdsMax;
+    if (list == PAMD_LIST_HALF && !half_ok)
+      return fail(PAMD_EUNSUPPORTED, "half lists need n_atoms <= %d * block and LDS for 2 slice arrays", fused_half_slots());
+    P.half = list == PAMD_LIST_HALF || (list == PAMD_LIST_AUTO && half_ok);
+    const size_t lds_r = fused_lds_bytes(N, P.cells.nc, true, P.half);
+    const size_t lds_g = fused_lds_bytes(N, P.cells.nc, false, P.half);
     if (lds_r <= kLdsMax) {
       P.r_in_lds = true;
       P.lds = lds_r;
@@ -343,6 +354,7 @@ FusedLaunch launch_of(const Plan& P) {
   L.grid = P.grid;
   L.r_in_lds = P.r_in_lds;
   L.f32 = P.f32;
+  L.half = P.half;
   L.lds_bytes = P.lds;
   return L;
 }
@@ -561,12 +573,20 @@ int pamd_autotune(const pamd_path* p, const pamd_potential* v, const double* x,
   if (v->kind == PAMD_LJ) {
     const int N = p->n_atoms;
     std::vector<int> blocks;
-    for (int b : {default_block(N), (int)align_up((size_t)N, 64), (int)align_up((size_t)(N + 3) / 4, 64), 256, 512})
+    for (int b : {default_block(N), (int)align_up((size_t)(N + 1) / 2, 64), 256, 512, 1024})
       if (b >= 64 && b <= 1024 && std::find(blocks.begin(), blocks.end(), b) == blocks.end()) blocks.push_back(b);
-    for (int b : blocks)
-      for (int tile : {2, 4, 8, 16, 32})
-        for (double skin : {0.2, 0.3, 0.45})
-          cands.push_back(pamd_tuning{PAMD_ALGO_FUSED, b, tile, 0, skin * v->sigma});
+    for (int list : {PAMD_LIST_HALF, PAMD_LIST_FULL})
+      for (int b : blocks)
+        for (int tile : {4, 8, 16, 32})
+          for (double skin : {0.2, 0.3, 0.45}) {
+            pamd_tuning c{};
+            c.algo = PAMD_ALGO_FUSED;
+            c.block = b;
+            c.tile = tile;
+            c.skin = skin * v->sigma;
+            c.neighbour_list = list;
+            cands.push_back(c);
+          }
   } else {
     cands.push_back(pamd_tuning{});
   }

@@ -119,7 +119,7 @@ int pamd_batch_create(int32_t n_paths, const pamd_path* paths, const pamd_potent
 
   // Lennard-Jones members: per-member tiles and lists, batch-wide launch shape.
   int max_n = 1;
-  size_t max_lds_r = 0, max_lds_g = 0, max_nbr = 0;
+  size_t max_lds_r = 0, max_lds_g = 0, max_lds_rh = 0, max_lds_gh = 0, max_nbr = 0;
   int64_t bnd_elems = 0;
   const double skin_in = tuning && tuning->skin > 0 ? tuning->skin : -1.0;
   for (int p : b->lj_ids) {
@@ -167,8 +167,10 @@ int pamd_batch_create(int32_t n_paths, const pamd_path* paths, const pamd_potent
     b->slots.push_back(p);
     b->max_tiles = std::max(b->max_tiles, a.n_tiles);
     max_n = std::max(max_n, N);
-    max_lds_r = std::max(max_lds_r, fused_lds_bytes(N, cc.nc, true));
-    max_lds_g = std::max(max_lds_g, fused_lds_bytes(N, cc.nc, false));
+    max_lds_r = std::max(max_lds_r, fused_lds_bytes(N, cc.nc, true, false));
+    max_lds_g = std::max(max_lds_g, fused_lds_bytes(N, cc.nc, false, false));
+    max_lds_rh = std::max(max_lds_rh, fused_lds_bytes(N, cc.nc, true, true));
+    max_lds_gh = std::max(max_lds_gh, fused_lds_bytes(N, cc.nc, false, true));
     max_nbr = std::max(max_nbr, (size_t)kmax * N);
   }
   // Work list: every tile of every member, largest (atoms x steps) first.
@@ -188,20 +190,28 @@ int pamd_batch_create(int32_t n_paths, const pamd_path* paths, const pamd_potent
   FusedLaunch& L = b->launch;
   L.f32 = b->f32;
   if (!b->lj_ids.empty()) {
-    if (max_lds_r <= kLdsMax) {
+    int per = (max_n + 1023) / 1024;
+    int block = tuning && tuning->block ? tuning->block
+                                        : (int)align_up((size_t)((max_n + per - 1) / per), 64);
+    L.block = std::max(64, std::min(1024, block));
+    const int list = tuning ? tuning->neighbour_list : PAMD_LIST_AUTO;
+    const bool half_ok = max_n <= fused_half_slots() * L.block && max_lds_gh <= kLdsMax;
+    if (list == PAMD_LIST_HALF && !half_ok) {
+      delete b;
+      return batch_fail(PAMD_EUNSUPPORTED, "half lists do not fit this batch");
+    }
+    L.half = list == PAMD_LIST_HALF || (list == PAMD_LIST_AUTO && half_ok);
+    const size_t lr = L.half ? max_lds_rh : max_lds_r, lg = L.half ? max_lds_gh : max_lds_g;
+    if (lr <= kLdsMax) {
       L.r_in_lds = true;
-      L.lds_bytes = max_lds_r;
-    } else if (max_lds_g <= kLdsMax) {
+      L.lds_bytes = lr;
+    } else if (lg <= kLdsMax) {
       L.r_in_lds = false;
-      L.lds_bytes = max_lds_g;
+      L.lds_bytes = lg;
     } else {
       delete b;
       return batch_fail(PAMD_EUNSUPPORTED, "batch member with %d atoms exceeds LDS", max_n);
     }
-    int block = tuning && tuning->block ? tuning->block
-                                        : (max_n <= 512 ? (int)align_up((size_t)max_n, 64)
-                                                        : (int)align_up((size_t)(max_n + 1) / 2, 64));
-    L.block = std::max(64, std::min(1024, block));
     L.grid = std::max(1, std::min<int>((int)b->items.size(), kMaxGrid));
   }
   b->nbr_stride = align_up(max_nbr, 128);

@@ -61,6 +61,7 @@ struct FusedLaunch {
   int grid;         // blocks
   bool r_in_lds;
   bool f32;
+  bool half;        // half neighbour lists with LDS atomics (else full lists)
   size_t lds_bytes;
 };
 
@@ -90,7 +91,8 @@ struct BatchBase {
   int32_t pad0;
 };
 
-size_t fused_lds_bytes(int n_atoms, int nc, bool r_in_lds);
+size_t fused_lds_bytes(int n_atoms, int nc, bool r_in_lds, bool half);
+int fused_half_slots();
 size_t plain_lds_bytes(int n_atoms, int nc);
 
 hipError_t launch_lj_fused(const PathArgs& a, const BlockScratch& s, const FusedLaunch& L,

@@ -6,39 +6,58 @@
 // s_n = |r_n|^2/(4 D dt) (Eq. 3), stores rho_n = w_n r_n for the whole slice,
 // then applies the Hessian K-sum to rho_n and writes
 //     g_n = c [rho_{n-1} - rho_n + (dt/gamma) H(x_n) rho_n],  c = 1/(2 D dt).
-// rho_{n-1} is carried in registers of the thread that owns the atom; at the
-// tile's first step it belongs to the previous tile, which writes c rho_{n0-1}
-// to a boundary buffer that the finalize kernel adds (fixed order, no atomics).
+// rho_{n-1} is kept per atom in block-private memory; at the tile's first step
+// it belongs to the previous tile, which writes c rho_{n0-1} to a boundary
+// buffer that the finalize kernel adds (fixed order, no atomics).
 //
 // Neighbour lists (radius r_c + skin) are built at the tile start from a cell
 // list in LDS and reused while no atom has moved more than skin/2 from where
 // the list was built (then every pair with r <= r_c at the current slice is
 // in the list); otherwise the list is rebuilt on the spot.  The cutoff test
-// itself is exact at every slice.
+// itself is exact at every slice.  At every build the atoms are re-sorted in
+// cell order inside LDS, so that threads of a wave handle neighbouring atoms
+// and read largely the same neighbour positions (LDS broadcast, few bank
+// conflicts).
+//
+// Two list kinds:
+//   full  every atom lists all its partners; each pair is evaluated twice and
+//         every sum has a fixed order (bitwise repeatable);
+//   half  each pair is listed once (half-space rule on the build-time
+//         displacement); the partner's share is added with LDS float64 atomics
+//         (half the pair arithmetic; sums are order-dependent at rounding level).
 #include "lj_pair.hpp"
 
 namespace pamd {
 
+constexpr int HALF_SLOTS = 2;  // atoms per thread supported by the half-list kernel
+
 struct TileLDS {
-  double* X;     // 3 * n_atoms, slice x_n (AoS)
-  double* R;     // 3 * n_atoms, rho_n (AoS), when kept in LDS
+  double* X;     // 3 * n_atoms, slice x_n, sorted slots (AoS)
+  double* R;     // 3 * n_atoms, rho_n, sorted slots (when kept in LDS)
+  double* ACC;   // 3 * n_atoms, partner-share accumulator (half lists)
   double* red;   // 32 doubles
+  int* perm;     // n_atoms: slot -> original atom index
+  int* perm2;    // n_atoms: scratch for re-sorting
   CellLDS cells;
 };
 
-__device__ inline TileLDS carve_lds(char* base, int n_atoms, int ncell, bool r_in_lds) {
+__device__ inline TileLDS carve_lds(char* base, int n_atoms, int ncell, bool r_in_lds,
+                                    bool half) {
   TileLDS t;
   size_t off = 0;
+  const size_t vec = sizeof(double) * 3 * (size_t)n_atoms;
   t.X = reinterpret_cast<double*>(base + off);
-  off += sizeof(double) * 3 * (size_t)n_atoms;
-  if (r_in_lds) {
-    t.R = reinterpret_cast<double*>(base + off);
-    off += sizeof(double) * 3 * (size_t)n_atoms;
-  } else {
-    t.R = nullptr;
-  }
+  off += vec;
+  t.R = r_in_lds ? reinterpret_cast<double*>(base + off) : nullptr;
+  off += r_in_lds ? vec : 0;
+  t.ACC = half ? reinterpret_cast<double*>(base + off) : nullptr;
+  off += half ? vec : 0;
   t.red = reinterpret_cast<double*>(base + off);
   off += sizeof(double) * 32;
+  t.perm = reinterpret_cast<int*>(base + off);
+  off += sizeof(int) * (size_t)n_atoms;
+  t.perm2 = reinterpret_cast<int*>(base + off);
+  off += sizeof(int) * (size_t)n_atoms;
   t.cells.tmp = reinterpret_cast<int*>(base + off);
   off += sizeof(int) * 16;
   t.cells.start = reinterpret_cast<int*>(base + off);
@@ -49,31 +68,205 @@ __device__ inline TileLDS carve_lds(char* base, int n_atoms, int ncell, bool r_i
   return t;
 }
 
-size_t fused_lds_bytes(int n_atoms, int nc, bool r_in_lds) {
+size_t fused_lds_bytes(int n_atoms, int nc, bool r_in_lds, bool half) {
   const size_t ncell = (size_t)nc * nc * nc;
-  size_t b = sizeof(double) * 3 * (size_t)n_atoms * (r_in_lds ? 2 : 1);
+  size_t b = sizeof(double) * 3 * (size_t)n_atoms * (1 + (r_in_lds ? 1 : 0) + (half ? 1 : 0));
   b += sizeof(double) * 32 + sizeof(int) * 16;
+  b += sizeof(int) * 2 * (size_t)n_atoms;
   b += sizeof(int) * (2 * ncell + 1);
   b += sizeof(int) * (size_t)n_atoms;
   return b;
 }
 
+int fused_half_slots() { return HALF_SLOTS; }
+
 // Per-block global scratch for one tile: lists and per-atom state that only
-// the owning thread touches (atom i is owned by thread i mod blockDim).
+// the owning thread touches.
 struct TileScratch {
-  uint16_t* nbr;   // kmax * n_atoms
+  uint16_t* nbr;   // kmax * n_atoms, entry k of slot s at [k * n_atoms + s]
   int* cnt;        // n_atoms
-  double* xref;    // 3 * n_atoms: positions at the last list build
-  double* rprev;   // 3 * n_atoms: rho_{n-1}
-  double* rglob;   // 3 * n_atoms: rho_n of every atom when not in LDS
+  double* xref;    // 3 * n_atoms: positions (sorted slots) at the last list build
+  double* rprev;   // 3 * n_atoms: rho_{n-1}, by original atom index
+  double* rglob;   // 3 * n_atoms: rho_n (sorted slots) when not in LDS; sort scratch
 };
 
-template <bool F32, bool RLDS>
+// Half-space rule: the pair is stored by the atom whose displacement to its
+// partner points "up" (z, then y, then x); exact ties fall back to slot order.
+__device__ __forceinline__ bool upper_half(double dx, double dy, double dz, int s, int t) {
+  if (dz != 0.0) return dz > 0.0;
+  if (dy != 0.0) return dy > 0.0;
+  if (dx != 0.0) return dx > 0.0;
+  return s < t;
+}
+
+// (Re)builds the neighbour lists of the slice in L.X.  With cells, atoms are
+// first re-sorted into cell order (slots and perm are rewritten).
+template <bool HALF>
+__device__ void rebuild(const PathArgs& a, TileLDS& L, const TileScratch& ts, double* tmp) {
+  const int N = a.n_atoms;
+  const int B = blockDim.x;
+  const double box = a.lj.box, ib = a.lj.inv_box;
+  if (a.nc > 0) {
+    build_cells(a.lj, L.X, N, a.nc, L.cells);
+    for (int s = threadIdx.x; s < N; s += B) {
+      const int old = L.cells.atoms[s];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) tmp[3 * s + c] = L.X[3 * old + c];
+      L.perm2[s] = L.perm[old];
+    }
+    __syncthreads();
+    for (int s = threadIdx.x; s < N; s += B) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) L.X[3 * s + c] = tmp[3 * s + c];
+      L.perm[s] = L.perm2[s];
+    }
+    __syncthreads();
+  }
+  const int nc = a.nc, reach = a.reach;
+  for (int s = threadIdx.x; s < N; s += B) {
+    const double xs = L.X[3 * s], ys = L.X[3 * s + 1], zs = L.X[3 * s + 2];
+    int cnt = 0;
+    bool over = false;
+    uint16_t* nb = ts.nbr + s;
+    auto visit = [&](int t) {
+      const double dx = min_image(xs - L.X[3 * t + 0], box, ib);
+      const double dy = min_image(ys - L.X[3 * t + 1], box, ib);
+      const double dz = min_image(zs - L.X[3 * t + 2], box, ib);
+      const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+      if (r2 <= a.rlist2 && (!HALF || upper_half(dx, dy, dz, s, t))) {
+        if (cnt < a.kmax)
+          nb[(size_t)cnt * N] = (uint16_t)t;
+        else
+          over = true;
+        ++cnt;
+      }
+    };
+    if (nc == 0) {
+      for (int t = 0; t < N; ++t)
+        if (t != s) visit(t);
+    } else {
+      const int cx = cell_coord(xs, box, ib, nc);
+      const int cy = cell_coord(ys, box, ib, nc);
+      const int cz = cell_coord(zs, box, ib, nc);
+      for (int oz = -reach; oz <= reach; ++oz) {
+        const int z = (cz + oz + nc) % nc;
+        for (int oy = -reach; oy <= reach; ++oy) {
+          const int y = (cy + oy + nc) % nc;
+          for (int ox = -reach; ox <= reach; ++ox) {
+            const int x = (cx + ox + nc) % nc;
+            const int c = (z * nc + y) * nc + x;
+            const int hi = L.cells.start[c + 1];
+            for (int t = L.cells.start[c]; t < hi; ++t)
+              if (t != s) visit(t);
+          }
+        }
+      }
+    }
+    ts.cnt[s] = over ? -1 : cnt;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) ts.xref[3 * s + c] = L.X[3 * s + c];
+  }
+}
+
+// Build-time half-space membership of pair (s, t) for the overflow scan.
+__device__ __forceinline__ bool ref_upper(const LJConst& lj, const double* xref, int s, int t) {
+  const double ux = min_image(xref[3 * s] - xref[3 * t], lj.box, lj.inv_box);
+  const double uy = min_image(xref[3 * s + 1] - xref[3 * t + 1], lj.box, lj.inv_box);
+  const double uz = min_image(xref[3 * s + 2] - xref[3 * t + 2], lj.box, lj.inv_box);
+  return upper_half(ux, uy, uz, s, t);
+}
+
+// Pair loop of pass 1 for slot s.  Returns the force on s from its list; with
+// half lists the partners' shares are added into ACC.
+template <bool F32, bool HALF>
+__device__ __forceinline__ void pass1_slot(const PathArgs& a, const TileLDS& L,
+                                           const TileScratch& ts, int s, double xs, double ys,
+                                           double zs, double& fx, double& fy, double& fz) {
+  const int N = a.n_atoms;
+  const LJConst& lj = a.lj;
+  fx = fy = fz = 0.0;
+  const int cnt = ts.cnt[s];
+  auto pair = [&](int t) {
+    const double dx = min_image(xs - L.X[3 * t + 0], lj.box, lj.inv_box);
+    const double dy = min_image(ys - L.X[3 * t + 1], lj.box, lj.inv_box);
+    const double dz = min_image(zs - L.X[3 * t + 2], lj.box, lj.inv_box);
+    const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+    if (r2 <= lj.rc2) {
+      double px = 0.0, py = 0.0, pz = 0.0;
+      PairMath<F32>::accum_force(lj, dx, dy, dz, r2, px, py, pz);
+      fx += px;
+      fy += py;
+      fz += pz;
+      if (HALF) {
+        unsafeAtomicAdd(&L.ACC[3 * t + 0], -px);
+        unsafeAtomicAdd(&L.ACC[3 * t + 1], -py);
+        unsafeAtomicAdd(&L.ACC[3 * t + 2], -pz);
+      }
+    }
+  };
+  if (cnt >= 0) {
+    const uint16_t* nb = ts.nbr + s;
+#pragma unroll 2
+    for (int k = 0; k < cnt; ++k) pair(nb[(size_t)k * N]);
+  } else {
+    // list overflow: scan every atom, keeping the build-time half-space rule
+    for (int t = 0; t < N; ++t) {
+      if (t == s) continue;
+      if (HALF && !ref_upper(lj, ts.xref, s, t)) continue;
+      pair(t);
+    }
+  }
+}
+
+// Pair loop of pass 2 for slot s: q_s = sum_t K_st (rho_s - rho_t).
+template <bool F32, bool HALF>
+__device__ __forceinline__ void pass2_slot(const PathArgs& a, const TileLDS& L, const double* R,
+                                           const TileScratch& ts, int s, double xs, double ys,
+                                           double zs, double rx, double ry, double rz,
+                                           double& qx, double& qy, double& qz) {
+  const int N = a.n_atoms;
+  const LJConst& lj = a.lj;
+  qx = qy = qz = 0.0;
+  const int cnt = ts.cnt[s];
+  auto pair = [&](int t) {
+    const double dx = min_image(xs - L.X[3 * t + 0], lj.box, lj.inv_box);
+    const double dy = min_image(ys - L.X[3 * t + 1], lj.box, lj.inv_box);
+    const double dz = min_image(zs - L.X[3 * t + 2], lj.box, lj.inv_box);
+    const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+    if (r2 <= lj.rc2) {
+      double kx = 0.0, ky = 0.0, kz = 0.0;
+      PairMath<F32>::accum_hv(lj, dx, dy, dz, r2, rx - R[3 * t + 0], ry - R[3 * t + 1],
+                              rz - R[3 * t + 2], kx, ky, kz);
+      qx += kx;
+      qy += ky;
+      qz += kz;
+      if (HALF) {
+        unsafeAtomicAdd(&L.ACC[3 * t + 0], -kx);
+        unsafeAtomicAdd(&L.ACC[3 * t + 1], -ky);
+        unsafeAtomicAdd(&L.ACC[3 * t + 2], -kz);
+      }
+    }
+  };
+  if (cnt >= 0) {
+    const uint16_t* nb = ts.nbr + s;
+#pragma unroll 2
+    for (int k = 0; k < cnt; ++k) pair(nb[(size_t)k * N]);
+  } else {
+    for (int t = 0; t < N; ++t) {
+      if (t == s) continue;
+      if (HALF && !ref_upper(lj, ts.xref, s, t)) continue;
+      pair(t);
+    }
+  }
+}
+
+template <bool F32, bool RLDS, bool HALF>
 __device__ void tile_body(const PathArgs& a, int tile, const TileScratch& ts, char* lds_base) {
   const int N = a.n_atoms;
   const int ncell = a.nc * a.nc * a.nc;
-  TileLDS L = carve_lds(lds_base, N, ncell, RLDS);
+  TileLDS L = carve_lds(lds_base, N, ncell, RLDS, HALF);
   double* R = RLDS ? L.R : ts.rglob;
+  double* sort_tmp = RLDS ? L.R : (HALF ? L.ACC : ts.rglob);
   const int64_t n0 = (int64_t)tile * a.tile;
   const int64_t n1 = min(n0 + (int64_t)a.tile, a.n_steps);
   const size_t slice = (size_t)3 * N;
@@ -82,6 +275,7 @@ __device__ void tile_body(const PathArgs& a, int tile, const TileScratch& ts, ch
   const double box = a.lj.box, ib = a.lj.inv_box;
 
   for (int i = threadIdx.x; i < N; i += B) {
+    L.perm[i] = i;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       L.X[3 * i + c] = a.x[(size_t)n0 * slice + (size_t)c * N + i];
@@ -97,40 +291,59 @@ __device__ void tile_body(const PathArgs& a, int tile, const TileScratch& ts, ch
 
     if (!need_build) {
       double m = 0.0;
-      for (int i = threadIdx.x; i < N; i += B) {
-        const double ux = min_image(L.X[3 * i + 0] - ts.xref[3 * i + 0], box, ib);
-        const double uy = min_image(L.X[3 * i + 1] - ts.xref[3 * i + 1], box, ib);
-        const double uz = min_image(L.X[3 * i + 2] - ts.xref[3 * i + 2], box, ib);
+      for (int s = threadIdx.x; s < N; s += B) {
+        const double ux = min_image(L.X[3 * s + 0] - ts.xref[3 * s + 0], box, ib);
+        const double uy = min_image(L.X[3 * s + 1] - ts.xref[3 * s + 1], box, ib);
+        const double uz = min_image(L.X[3 * s + 2] - ts.xref[3 * s + 2], box, ib);
         m = fmax(m, fma(ux, ux, fma(uy, uy, uz * uz)));
       }
       m = block_max_all(m, L.red);
       need_build = !(m <= a.half_skin2);
     }
     if (need_build) {
-      if (a.nc > 0) build_cells(a.lj, L.X, N, a.nc, L.cells);
-      for (int i = threadIdx.x; i < N; i += B) {
-        ts.cnt[i] = build_list(a.lj, L.X, N, a.nc, a.reach, L.cells, a.rlist2, a.kmax,
-                               ts.nbr + i, i);
-#pragma unroll
-        for (int c = 0; c < 3; ++c) ts.xref[3 * i + c] = L.X[3 * i + c];
-      }
+      rebuild<HALF>(a, L, ts, sort_tmp);
       need_build = false;
     }
+    if (HALF) {
+      for (int e = threadIdx.x; e < 3 * N; e += B) L.ACC[e] = 0.0;
+    }
+    __syncthreads();  // lists, slots and ACC ready
 
     // ---- pass 1: force, residual, per-step action ----
     double s_loc = 0.0, e_loc = 0.0;
-    for (int i = threadIdx.x; i < N; i += B) {
-      const double xi = L.X[3 * i + 0], yi = L.X[3 * i + 1], zi = L.X[3 * i + 2];
+    for (int s = threadIdx.x; s < N; s += B) {
       double f[3];
-      force_on<F32>(a.lj, L.X, N, ts.nbr + i, ts.cnt[i], i, xi, yi, zi, f[0], f[1], f[2]);
-      const double xo[3] = {xi, yi, zi};
+      pass1_slot<F32, HALF>(a, L, ts, s, L.X[3 * s], L.X[3 * s + 1], L.X[3 * s + 2], f[0], f[1],
+                            f[2]);
+      if (HALF) {
+        // own partial force waits in R until every partner share has arrived
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const double d = min_image(xnext[(size_t)c * N + i] - xo[c], box, ib);
-        const double r = fma(-a.mu_dt, f[c], d);
-        s_loc = fma(r, r, s_loc);
-        e_loc = fma(r - d, r + d, e_loc);
-        if (grad) R[3 * i + c] = w * r;
+        for (int c = 0; c < 3; ++c) R[3 * s + c] = f[c];
+      } else {
+        const int o = L.perm[s];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const double d = min_image(xnext[(size_t)c * N + o] - L.X[3 * s + c], box, ib);
+          const double r = fma(-a.mu_dt, f[c], d);
+          s_loc = fma(r, r, s_loc);
+          e_loc = fma(r - d, r + d, e_loc);
+          if (grad) R[3 * s + c] = w * r;
+        }
+      }
+    }
+    if (HALF) {
+      __syncthreads();  // every partner share is in ACC
+      for (int s = threadIdx.x; s < N; s += B) {
+        const int o = L.perm[s];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const double f = R[3 * s + c] + L.ACC[3 * s + c];
+          const double d = min_image(xnext[(size_t)c * N + o] - L.X[3 * s + c], box, ib);
+          const double r = fma(-a.mu_dt, f, d);
+          s_loc = fma(r, r, s_loc);
+          e_loc = fma(r - d, r + d, e_loc);
+          R[3 * s + c] = w * r;
+        }
       }
     }
     const double s_sum = block_sum(s_loc, L.red);
@@ -142,38 +355,72 @@ __device__ void tile_body(const PathArgs& a, int tile, const TileScratch& ts, ch
 
     // ---- pass 2: Hessian-vector product and gradient ----
     if (grad) {
-      __syncthreads();  // R holds rho_n of every atom
-      for (int i = threadIdx.x; i < N; i += B) {
-        const double xi = L.X[3 * i + 0], yi = L.X[3 * i + 1], zi = L.X[3 * i + 2];
-        const double rx = R[3 * i + 0], ry = R[3 * i + 1], rz = R[3 * i + 2];
-        double q[3];
-        hv_on<F32>(a.lj, L.X, R, N, ts.nbr + i, ts.cnt[i], i, xi, yi, zi, rx, ry, rz, q[0],
-                   q[1], q[2]);
-        const double rho[3] = {rx, ry, rz};
+      if (HALF) {
+        for (int e = threadIdx.x; e < 3 * N; e += B) L.ACC[e] = 0.0;
+      }
+      __syncthreads();  // R holds rho_n of every atom; ACC cleared
+      if (!HALF) {
+        for (int s = threadIdx.x; s < N; s += B) {
+          double q[3];
+          pass2_slot<F32, false>(a, L, R, ts, s, L.X[3 * s], L.X[3 * s + 1], L.X[3 * s + 2],
+                                 R[3 * s], R[3 * s + 1], R[3 * s + 2], q[0], q[1], q[2]);
+          const int o = L.perm[s];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          const double g = a.c * (ts.rprev[3 * i + c] - rho[c] + a.mu_dt * q[c]);
-          a.grad[(size_t)n * slice + (size_t)c * N + i] = g;
-          ts.rprev[3 * i + c] = rho[c];
+          for (int c = 0; c < 3; ++c) {
+            const double rho = R[3 * s + c];
+            const double g = a.c * (ts.rprev[3 * o + c] - rho + a.mu_dt * q[c]);
+            a.grad[(size_t)n * slice + (size_t)c * N + o] = g;
+            ts.rprev[3 * o + c] = rho;
+          }
+        }
+      } else {
+        // own partial q stays in registers until the partner shares arrive
+        double q[HALF_SLOTS][3];
+#pragma unroll
+        for (int k = 0; k < HALF_SLOTS; ++k) {
+          const int s = threadIdx.x + k * B;
+          q[k][0] = q[k][1] = q[k][2] = 0.0;
+          if (s < N)
+            pass2_slot<F32, true>(a, L, R, ts, s, L.X[3 * s], L.X[3 * s + 1], L.X[3 * s + 2],
+                                  R[3 * s], R[3 * s + 1], R[3 * s + 2], q[k][0], q[k][1],
+                                  q[k][2]);
+        }
+        __syncthreads();  // every partner share is in ACC
+#pragma unroll
+        for (int k = 0; k < HALF_SLOTS; ++k) {
+          const int s = threadIdx.x + k * B;
+          if (s < N) {
+            const int o = L.perm[s];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+              const double rho = R[3 * s + c];
+              const double g =
+                  a.c * (ts.rprev[3 * o + c] - rho + a.mu_dt * (q[k][c] + L.ACC[3 * s + c]));
+              a.grad[(size_t)n * slice + (size_t)c * N + o] = g;
+              ts.rprev[3 * o + c] = rho;
+            }
+          }
         }
       }
     }
-    __syncthreads();  // every read of X (and R) for slice n is done
-    for (int i = threadIdx.x; i < N; i += B) {
+    __syncthreads();  // every read of X (and R, ACC) for slice n is done
+    for (int s = threadIdx.x; s < N; s += B) {
+      const int o = L.perm[s];
 #pragma unroll
-      for (int c = 0; c < 3; ++c) L.X[3 * i + c] = xnext[(size_t)c * N + i];
+      for (int c = 0; c < 3; ++c) L.X[3 * s + c] = xnext[(size_t)c * N + o];
     }
   }
 
   if (grad) {
-    for (int i = threadIdx.x; i < N; i += B) {
+    __syncthreads();
+    for (int o = threadIdx.x; o < N; o += B) {
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        const double v = a.c * ts.rprev[3 * i + c];
+        const double v = a.c * ts.rprev[3 * o + c];
         if (n1 == a.n_steps)
-          a.grad[(size_t)a.n_steps * slice + (size_t)c * N + i] = v;
+          a.grad[(size_t)a.n_steps * slice + (size_t)c * N + o] = v;
         else
-          a.bnd[(size_t)tile * slice + (size_t)c * N + i] = v;
+          a.bnd[(size_t)tile * slice + (size_t)c * N + o] = v;
       }
     }
   }
@@ -190,11 +437,12 @@ __device__ __forceinline__ TileScratch block_scratch(const BlockScratch& s) {
   return t;
 }
 
-template <bool F32, bool RLDS>
+template <bool F32, bool RLDS, bool HALF>
 __global__ void __launch_bounds__(1024) lj_fused_kernel(PathArgs a, BlockScratch s) {
   extern __shared__ __align__(16) char lds[];
   const TileScratch ts = block_scratch(s);
-  for (int t = blockIdx.x; t < a.n_tiles; t += gridDim.x) tile_body<F32, RLDS>(a, t, ts, lds);
+  for (int t = blockIdx.x; t < a.n_tiles; t += gridDim.x)
+    tile_body<F32, RLDS, HALF>(a, t, ts, lds);
 }
 
 __device__ __forceinline__ PathArgs member_args(const BatchMember& m, const BatchBase& b) {
@@ -211,7 +459,7 @@ __device__ __forceinline__ PathArgs member_args(const BatchMember& m, const Batc
 }
 
 // Persistent batch kernel: workgroups pull (path, tile) items, largest first.
-template <bool F32, bool RLDS>
+template <bool F32, bool RLDS, bool HALF>
 __global__ void __launch_bounds__(1024) lj_batch_kernel(const BatchMember* members,
                                                         BatchBase base, const BatchItem* items,
                                                         int n_items, int* counter,
@@ -227,7 +475,7 @@ __global__ void __launch_bounds__(1024) lj_batch_kernel(const BatchMember* membe
     if (it >= n_items) break;
     const BatchItem item = items[it];
     const PathArgs a = member_args(members[item.path], base);
-    tile_body<F32, RLDS>(a, item.tile, ts, lds);
+    tile_body<F32, RLDS, HALF>(a, item.tile, ts, lds);
   }
 }
 
@@ -276,10 +524,10 @@ __global__ void batch_finalize_kernel(const BatchMember* members, BatchBase base
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
-template <bool F32, bool RLDS>
+template <bool F32, bool RLDS, bool HALF>
 static hipError_t launch_fused_t(const PathArgs& a, const BlockScratch& s, const FusedLaunch& L,
                                  hipStream_t st) {
-  auto kern = lj_fused_kernel<F32, RLDS>;
+  auto kern = lj_fused_kernel<F32, RLDS, HALF>;
   hipError_t e = hipFuncSetAttribute((const void*)kern,
                                      hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)L.lds_bytes);
@@ -288,11 +536,11 @@ static hipError_t launch_fused_t(const PathArgs& a, const BlockScratch& s, const
   return hipGetLastError();
 }
 
-template <bool F32, bool RLDS>
+template <bool F32, bool RLDS, bool HALF>
 static hipError_t launch_batch_t(const BatchMember* m, const BatchBase& b, const BatchItem* it,
                                  int n, int* ctr, const BlockScratch& s, const FusedLaunch& L,
                                  hipStream_t st) {
-  auto kern = lj_batch_kernel<F32, RLDS>;
+  auto kern = lj_batch_kernel<F32, RLDS, HALF>;
   hipError_t e = hipFuncSetAttribute((const void*)kern,
                                      hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)L.lds_bytes);
@@ -301,9 +549,17 @@ static hipError_t launch_batch_t(const BatchMember* m, const BatchBase& b, const
   return hipGetLastError();
 }
 
-#define PAMD_DISPATCH(FN, ...)                                                  \
-  return L.f32 ? (L.r_in_lds ? FN<true, true>(__VA_ARGS__) : FN<true, false>(__VA_ARGS__)) \
-               : (L.r_in_lds ? FN<false, true>(__VA_ARGS__) : FN<false, false>(__VA_ARGS__));
+#define PAMD_DISPATCH3(FN, F32, ...)                                                      \
+  if (L.half)                                                                             \
+    return L.r_in_lds ? FN<F32, true, true>(__VA_ARGS__) : FN<F32, false, true>(__VA_ARGS__); \
+  return L.r_in_lds ? FN<F32, true, false>(__VA_ARGS__) : FN<F32, false, false>(__VA_ARGS__);
+
+#define PAMD_DISPATCH(FN, ...)             \
+  if (L.f32) {                             \
+    PAMD_DISPATCH3(FN, true, __VA_ARGS__)  \
+  } else {                                 \
+    PAMD_DISPATCH3(FN, false, __VA_ARGS__) \
+  }
 
 hipError_t launch_lj_fused(const PathArgs& a, const BlockScratch& s, const FusedLaunch& L,
                            hipStream_t st) {

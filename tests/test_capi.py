@@ -113,7 +113,8 @@ def test_harmonic_rejects_box_and_unknown_kind():
 
 
 @pytest.mark.parametrize("field,value", [("algo", 5), ("block", 100), ("block", 2048),
-                                         ("tile", -1), ("max_neighbours", -3)])
+                                         ("tile", -1), ("max_neighbours", -3),
+                                         ("neighbour_list", 7)])
 def test_tuning_validation(field, value):
     t = P.make_tuning()
     setattr(t, field, value)
@@ -136,6 +137,14 @@ def test_null_pointers_and_workspace():
     code = lib.pamd_excess_action(ctypes.byref(path), ctypes.byref(pot), None, FAKE, None, None,
                                   FAKE, ctypes.c_size_t(need), None)
     assert code == _lib.PAMD_EINVAL
+
+
+def test_half_list_needs_room():
+    # 864 atoms with 64-thread blocks cannot hold two slots per thread
+    t = P.make_tuning("fused", block=64, neighbour_list="half")
+    assert ws_size(lj_path(), lj_pot(), t)[0] == _lib.PAMD_EUNSUPPORTED
+    t = P.make_tuning("fused", block=448, neighbour_list="half")
+    assert ws_size(lj_path(), lj_pot(), t)[0] == 0
 
 
 def test_workspace_grows_with_problem_and_plain_form():

@@ -92,18 +92,20 @@ def test_lj108_fp32_force_plain(device, lj108, lj108_ref):
     check(w, X, precision="fp32_force", tuning=P.make_tuning("plain"), ref=lj108_ref)
 
 
+@pytest.mark.parametrize("nlist", ["full", "half"])
 @pytest.mark.parametrize("tile,skin,kmax", [(1, 0.3, 0), (7, 0.3, 0), (16, 1e-6, 0),
                                             (32, 0.9, 0), (5, 0.3, 4), (300, 0.3, 0)])
-def test_lj108_tiles_skins_overflow(device, lj108, lj108_ref, tile, skin, kmax):
+def test_lj108_tiles_skins_overflow(device, lj108, lj108_ref, tile, skin, kmax, nlist):
     w, X = lj108
-    check(w, X, tuning=P.make_tuning("fused", tile=tile, skin=skin, max_neighbours=kmax),
-          ref=lj108_ref)
+    check(w, X, tuning=P.make_tuning("fused", tile=tile, skin=skin, max_neighbours=kmax,
+                                     neighbour_list=nlist), ref=lj108_ref)
 
 
-@pytest.mark.parametrize("block", [64, 128, 192, 1024])
-def test_lj108_block_sizes(device, lj108, lj108_ref, block):
+@pytest.mark.parametrize("block,nlist", [(64, "half"), (128, "half"), (192, "full"),
+                                         (1024, "half"), (64, "full")])
+def test_lj108_block_sizes(device, lj108, lj108_ref, block, nlist):
     w, X = lj108
-    check(w, X, tuning=P.make_tuning("fused", block=block), ref=lj108_ref)
+    check(w, X, tuning=P.make_tuning("fused", block=block, neighbour_list=nlist), ref=lj108_ref)
 
 
 def test_lj108_step_weights(device, lj108):
@@ -140,10 +142,11 @@ def test_lj108_action_only_matches(device, lj108, lj108_ref):
     assert rel(float(act.item()), math.fsum(lj108_ref[0].tolist())) <= ACTION_TOL
 
 
-def test_bitwise_repeatable(device, lj108):
+def test_bitwise_repeatable_full_lists(device, lj108):
     w, X = lj108
-    a1 = run(w, X)
-    a2 = run(w, X)
+    t = P.make_tuning("fused", neighbour_list="full")
+    a1 = run(w, X, tuning=t)
+    a2 = run(w, X, tuning=t)
     assert a1[0] == a2[0]
     assert np.array_equal(a1[1], a2[1]) and np.array_equal(a1[2], a2[2])
 
@@ -166,6 +169,8 @@ def test_lj864_em_ragged_tiles(device):
     ref = oracle_full(w, X)
     check(w, X, ref=ref)
     check(w, X, tuning=P.make_tuning("fused", tile=7), ref=ref)
+    check(w, X, tuning=P.make_tuning("fused", tile=6, neighbour_list="full"), ref=ref)
+    check(w, X, tuning=P.make_tuning("fused", tile=9, block=448), ref=ref)
     check(w, X, tuning=P.make_tuning("plain"), ref=ref)
     check(w, X, precision="fp32_force", ref=ref)
 
@@ -219,6 +224,9 @@ def test_lj864_full_size_fused_equals_plain(device, lj864_full):
     S2, s2, g2 = run(w, X, tuning=P.make_tuning("plain"))
     assert rel(S1, S2) <= ACTION_TOL
     assert rel_inf(g1, g2) <= GRAD_TOL
+    S4, s4, g4 = run(w, X, tuning=P.make_tuning("fused", neighbour_list="full"))
+    assert rel(S1, S4) <= ACTION_TOL
+    assert rel_inf(g1, g4) <= GRAD_TOL
     S3, s3, g3 = run(w, X, precision="fp32_force")
     e_s, e_g = rel(S3, S1), rel_inf(g3, g1)
     print(f"lj864 full FP32-force vs FP64: action rel {e_s:.2e}, grad rel {e_g:.2e}")
