@@ -129,6 +129,10 @@ def main(argv=None) -> int:
     ap.add_argument("--workload", default="lj864")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--autotune", action="store_true")
+    ap.add_argument("--list", choices=["auto", "full", "half"], default="auto")
+    ap.add_argument("--tile", type=int, default=0)
+    ap.add_argument("--skin", type=float, default=0.0)
+    ap.add_argument("--block", type=int, default=0)
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the time-sharded "
@@ -154,7 +158,13 @@ def main(argv=None) -> int:
     precision = "fp32_force" if args.variant == "fp32_force" else "fp64"
     path = P.make_path(w.n_steps, w.n_atoms, 3, w.dt, w.D, w.gamma, precision)
     pot = P.make_potential("lj", eps=w.eps, sigma=w.sigma, rc=w.cutoff, box=w.box)
-    tuning = P.make_tuning("plain") if args.variant == "plain" else None
+    if args.variant == "plain":
+        tuning = P.make_tuning("plain")
+    elif args.list != "auto" or args.tile or args.skin or args.block:
+        tuning = P.make_tuning("fused", block=args.block, tile=args.tile, skin=args.skin,
+                               neighbour_list=args.list)
+    else:
+        tuning = None
     x = torch.from_numpy(X).to(dev)
     grad = torch.empty_like(x)
     act = torch.empty(1, dtype=torch.float64, device=dev)
@@ -216,6 +226,7 @@ def main(argv=None) -> int:
         "data": "synthetic",
         "config": {"workload": f"LJ {w.n_atoms} atoms x {w.n_steps} steps, rho 0.8442, T 1, "
                                f"rc 2.5, dt 1e-4, {args.variant}",
+                   "neighbour_list": args.list,
                    "n_atoms": w.n_atoms, "n_steps": w.n_steps, "variant": args.variant,
                    "parallelism": "single GPU"},
         "roofline": roof,
