@@ -49,14 +49,18 @@ def test_gradcheck_tiny(device):
                                     eps=1e-6, atol=1e-4, rtol=1e-6)
 
 
+# Graph replays are compared bit for bit, so these use the repeatable (full-list) form.
+FULL = P.make_tuning("fused", neighbour_list="full")
+
+
 def test_library_graph_replays_match_eager(device, case):
     w, X, _ = case
     path, pot = lib_descriptors(w)
     x = torch.from_numpy(X.copy()).cuda()
-    ws = P.workspace(P.pamd_workspace_size(path, pot))
+    ws = P.workspace(P.pamd_workspace_size(path, pot, FULL))
     g_e = torch.empty_like(x)
     a_e = torch.empty(1, dtype=torch.float64, device="cuda")
-    P.pamd_action_grad(path, pot, x, g_e, action=a_e, ws=ws)
+    P.pamd_action_grad(path, pot, x, g_e, action=a_e, ws=ws, tuning=FULL)
     torch.cuda.synchronize()
     g_c = torch.zeros_like(x)
     a_c = torch.zeros(1, dtype=torch.float64, device="cuda")
@@ -64,7 +68,7 @@ def test_library_graph_replays_match_eager(device, case):
     graph = P.PamdGraph()
     with torch.cuda.stream(s):
         graph.begin(s)
-        P.pamd_action_grad(path, pot, x, g_c, action=a_c, ws=ws, stream=s)
+        P.pamd_action_grad(path, pot, x, g_c, action=a_c, ws=ws, stream=s, tuning=FULL)
         graph.end(s)
     for rep in range(3):
         g_c.zero_()
@@ -82,22 +86,46 @@ def test_torch_cuda_graph_capture(device, case):
     w, X, _ = case
     path, pot = lib_descriptors(w)
     x = torch.from_numpy(X.copy()).cuda()
-    ws = P.workspace(P.pamd_workspace_size(path, pot))
+    ws = P.workspace(P.pamd_workspace_size(path, pot, FULL))
     g_e = torch.empty_like(x)
     a_e = torch.empty(1, dtype=torch.float64, device="cuda")
-    P.pamd_action_grad(path, pot, x, g_e, action=a_e, ws=ws)
+    P.pamd_action_grad(path, pot, x, g_e, action=a_e, ws=ws, tuning=FULL)
     torch.cuda.synchronize()
     g_c = torch.empty_like(x)
     a_c = torch.empty(1, dtype=torch.float64, device="cuda")
     cg = torch.cuda.CUDAGraph()
     with torch.cuda.graph(cg):
-        P.pamd_action_grad(path, pot, x, g_c, action=a_c, ws=ws)
+        P.pamd_action_grad(path, pot, x, g_c, action=a_c, ws=ws, tuning=FULL)
     for rep in range(3):
         g_c.fill_(0.0)
         torch.cuda.synchronize()
         cg.replay()
         torch.cuda.synchronize()
         assert torch.equal(g_c, g_e) and torch.equal(a_c, a_e), rep
+
+
+def test_half_list_graph_replays_within_rounding(device, case):
+    w, X, (s_ref, g_ref) = case
+    path, pot = lib_descriptors(w)
+    half = P.make_tuning("fused", neighbour_list="half")
+    x = torch.from_numpy(X.copy()).cuda()
+    ws = P.workspace(P.pamd_workspace_size(path, pot, half))
+    g_c = torch.zeros_like(x)
+    a_c = torch.zeros(1, dtype=torch.float64, device="cuda")
+    s = torch.cuda.Stream()
+    graph = P.PamdGraph()
+    with torch.cuda.stream(s):
+        graph.begin(s)
+        P.pamd_action_grad(path, pot, x, g_c, action=a_c, ws=ws, stream=s, tuning=half)
+        graph.end(s)
+    for rep in range(3):
+        g_c.zero_()
+        torch.cuda.synchronize()
+        graph.launch(s)
+        s.synchronize()
+        assert rel(float(a_c.item()), math.fsum(s_ref.tolist())) <= 1e-12, rep
+        assert rel_inf(g_c.cpu().numpy(), g_ref) <= 1e-10, rep
+    graph.close()
 
 
 def test_autotune_then_cached_choice_is_exact(device, case):
