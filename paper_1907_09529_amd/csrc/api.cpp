@@ -239,6 +239,7 @@ int make_plan(const pamd_path* p, const pamd_potential* v, const pamd_tuning* t_
     P.cells = choose_cells(L, radius, N);
     P.kmax = t.max_neighbours > 0 ? std::min(t.max_neighbours, std::max(1, N - 1))
                                   : default_kmax(L, radius, N);
+    P.kmax = (int)align_up((size_t)P.kmax, 8);  // lists are read in chunks of 8
     P.block = t.block ? t.block : (have_cache && cached.block ? cached.block : default_block(N));
     int tile = t.tile ? t.tile : (have_cache && cached.tile ? cached.tile : 0);
     if (tile <= 0) tile = (int)std::max<int64_t>(1, std::min<int64_t>(32, P.steps / 512));

@@ -133,6 +133,7 @@ int pamd_batch_create(int32_t n_paths, const pamd_path* paths, const pamd_potent
     int kmax = (int)align_up((size_t)std::ceil(1.3 * 4.0 / 3.0 * M_PI * radius * radius * radius * rho + 24.0), 8);
     if (tuning && tuning->max_neighbours > 0) kmax = tuning->max_neighbours;
     kmax = std::max(1, std::min(kmax, std::max(1, N - 1)));
+    kmax = (int)align_up((size_t)kmax, 8);  // lists are read in chunks of 8
     int tile = tuning && tuning->tile > 0 ? tuning->tile
                                           : (int)std::max(4, std::min(64, (int)std::ceil(16384.0 / N)));
     tile = (int)std::min<int64_t>(tile, P.n_steps);

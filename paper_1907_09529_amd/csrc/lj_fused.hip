@@ -83,7 +83,7 @@ int fused_half_slots() { return HALF_SLOTS; }
 // Per-block global scratch for one tile: lists and per-atom state that only
 // the owning thread touches.
 struct TileScratch {
-  uint16_t* nbr;   // kmax * n_atoms, entry k of slot s at [k * n_atoms + s]
+  uint16_t* nbr;   // kmax (multiple of 8) * n_atoms: chunks of 8 entries, [(k/8) N + s] * 8 + k%8
   int* cnt;        // n_atoms
   double* xref;    // 3 * n_atoms: positions (sorted slots) at the last list build
   double* rprev;   // 3 * n_atoms: rho_{n-1}, by original atom index
@@ -127,7 +127,8 @@ __device__ void rebuild(const PathArgs& a, TileLDS& L, const TileScratch& ts, do
     const double xs = L.X[3 * s], ys = L.X[3 * s + 1], zs = L.X[3 * s + 2];
     int cnt = 0;
     bool over = false;
-    uint16_t* nb = ts.nbr + s;
+    uint16_t* nb = ts.nbr + (size_t)s * 8;   // entry k at nb[(k >> 3) * 8 N + (k & 7)]
+    const size_t chunk = (size_t)8 * N;
     auto visit = [&](int t) {
       const double dx = min_image(xs - L.X[3 * t + 0], box, ib);
       const double dy = min_image(ys - L.X[3 * t + 1], box, ib);
@@ -135,7 +136,7 @@ __device__ void rebuild(const PathArgs& a, TileLDS& L, const TileScratch& ts, do
       const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
       if (r2 <= a.rlist2 && (!HALF || upper_half(dx, dy, dz, s, t))) {
         if (cnt < a.kmax)
-          nb[(size_t)cnt * N] = (uint16_t)t;
+          nb[(size_t)(cnt >> 3) * chunk + (cnt & 7)] = (uint16_t)t;
         else
           over = true;
         ++cnt;
@@ -148,20 +149,34 @@ __device__ void rebuild(const PathArgs& a, TileLDS& L, const TileScratch& ts, do
       const int cx = cell_coord(xs, box, ib, nc);
       const int cy = cell_coord(ys, box, ib, nc);
       const int cz = cell_coord(zs, box, ib, nc);
+      // stencil rows: atoms of cells (x0..x1, y, z) are contiguous slots after
+      // the cell-order sort, so each row is one or two slot ranges
       for (int oz = -reach; oz <= reach; ++oz) {
-        const int z = (cz + oz + nc) % nc;
+        int z = cz + oz;
+        z += z < 0 ? nc : (z >= nc ? -nc : 0);
         for (int oy = -reach; oy <= reach; ++oy) {
-          const int y = (cy + oy + nc) % nc;
-          for (int ox = -reach; ox <= reach; ++ox) {
-            const int x = (cx + ox + nc) % nc;
-            const int c = (z * nc + y) * nc + x;
-            const int hi = L.cells.start[c + 1];
-            for (int t = L.cells.start[c]; t < hi; ++t)
+          int y = cy + oy;
+          y += y < 0 ? nc : (y >= nc ? -nc : 0);
+          const int row = (z * nc + y) * nc;
+          const int x0 = cx - reach, x1 = cx + reach;
+          if (x0 >= 0 && x1 < nc) {
+            const int hi = L.cells.start[row + x1 + 1];
+            for (int t = L.cells.start[row + x0]; t < hi; ++t)
               if (t != s) visit(t);
+          } else {
+            for (int ox = -reach; ox <= reach; ++ox) {
+              int x = cx + ox;
+              x += x < 0 ? nc : (x >= nc ? -nc : 0);
+              const int hi = L.cells.start[row + x + 1];
+              for (int t = L.cells.start[row + x]; t < hi; ++t)
+                if (t != s) visit(t);
+            }
           }
         }
       }
     }
+    if (!over)  // pad the last chunk with the slot itself (read as invalid)
+      for (int k = cnt; k & 7; ++k) nb[(size_t)(k >> 3) * chunk + (k & 7)] = (uint16_t)s;
     ts.cnt[s] = over ? -1 : cnt;
 #pragma unroll
     for (int c = 0; c < 3; ++c) ts.xref[3 * s + c] = L.X[3 * s + c];
@@ -176,88 +191,148 @@ __device__ __forceinline__ bool ref_upper(const LJConst& lj, const double* xref,
   return upper_half(ux, uy, uz, s, t);
 }
 
-// Pair loop of pass 1 for slot s.  Returns the force on s from its list; with
-// half lists the partners' shares are added into ACC.
-template <bool F32, bool HALF>
-__device__ __forceinline__ void pass1_slot(const PathArgs& a, const TileLDS& L,
-                                           const TileScratch& ts, int s, double xs, double ys,
-                                           double zs, double& fx, double& fy, double& fz) {
+// Visits the list of slot s: chunks of 8 uint16 entries, chunk c at
+// nbr[(c * N + s) * 8]; the next chunk is fetched while the current one is
+// evaluated.  Entries past cnt are padding (the slot itself) and are passed
+// with valid = false.  An overflowed list (cnt < 0) visits every atom of the
+// slot's half (or all atoms with full lists) instead.
+template <bool HALF, typename Pair>
+__device__ __forceinline__ void for_each_partner(const PathArgs& a, const TileScratch& ts, int s,
+                                                 Pair&& pair) {
   const int N = a.n_atoms;
-  const LJConst& lj = a.lj;
-  fx = fy = fz = 0.0;
   const int cnt = ts.cnt[s];
-  auto pair = [&](int t) {
-    const double dx = min_image(xs - L.X[3 * t + 0], lj.box, lj.inv_box);
-    const double dy = min_image(ys - L.X[3 * t + 1], lj.box, lj.inv_box);
-    const double dz = min_image(zs - L.X[3 * t + 2], lj.box, lj.inv_box);
-    const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
-    if (r2 <= lj.rc2) {
-      double px = 0.0, py = 0.0, pz = 0.0;
-      PairMath<F32>::accum_force(lj, dx, dy, dz, r2, px, py, pz);
-      fx += px;
-      fy += py;
-      fz += pz;
-      if (HALF) {
-        unsafeAtomicAdd(&L.ACC[3 * t + 0], -px);
-        unsafeAtomicAdd(&L.ACC[3 * t + 1], -py);
-        unsafeAtomicAdd(&L.ACC[3 * t + 2], -pz);
-      }
-    }
-  };
   if (cnt >= 0) {
-    const uint16_t* nb = ts.nbr + s;
-#pragma unroll 2
-    for (int k = 0; k < cnt; ++k) pair(nb[(size_t)k * N]);
+    const uint4* nb = reinterpret_cast<const uint4*>(ts.nbr) + s;
+    const int nch = (cnt + 7) >> 3;
+    uint4 cur = make_uint4(0u, 0u, 0u, 0u);
+    if (nch > 0) cur = nb[0];
+    for (int ch = 0; ch < nch; ++ch) {
+      uint4 nxt = cur;
+      if (ch + 1 < nch) nxt = nb[(size_t)(ch + 1) * N];
+      const int k0 = ch * 8;
+      const uint32_t w[4] = {cur.x, cur.y, cur.z, cur.w};
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int t = (int)((w[e >> 1] >> (16 * (e & 1))) & 0xffffu);
+        pair(t, k0 + e < cnt);
+      }
+      cur = nxt;
+    }
   } else {
-    // list overflow: scan every atom, keeping the build-time half-space rule
     for (int t = 0; t < N; ++t) {
       if (t == s) continue;
-      if (HALF && !ref_upper(lj, ts.xref, s, t)) continue;
-      pair(t);
+      if (HALF && !ref_upper(a.lj, ts.xref, s, t)) continue;
+      pair(t, true);
     }
   }
 }
 
-// Pair loop of pass 2 for slot s: q_s = sum_t K_st (rho_s - rho_t).
+// Pass 1 for slot s: force on s from its list; with half lists the partners'
+// shares are added into ACC.
+template <bool F32, bool HALF>
+__device__ __forceinline__ void pass1_slot(const PathArgs& a, const TileLDS& L,
+                                           const TileScratch& ts, int s, double xs, double ys,
+                                           double zs, double& fx, double& fy, double& fz) {
+  const LJConst& lj = a.lj;
+  fx = fy = fz = 0.0;
+  for_each_partner<HALF>(a, ts, s, [&](int t, bool valid) {
+    const double dx = min_image(xs - L.X[3 * t + 0], lj.box, lj.inv_box);
+    const double dy = min_image(ys - L.X[3 * t + 1], lj.box, lj.inv_box);
+    const double dz = min_image(zs - L.X[3 * t + 2], lj.box, lj.inv_box);
+    const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+    const bool ok = valid && r2 <= lj.rc2;
+    double px, py, pz;
+    if constexpr (F32) {
+      const float ir = rsqrt_f32(ok ? (float)r2 : 1.0f);
+      const float ir2 = ir * ir;
+      const float sr2 = (float)lj.sig2 * ir2;
+      const float sr6 = sr2 * sr2 * sr2;
+      float fsf = fmaf((float)lj.a24 * ir2 * sr6, fmaf(2.0f, sr6, -1.0f), (float)lj.duc * ir);
+      fsf = ok ? fsf : 0.0f;
+      px = (double)(fsf * (float)dx);
+      py = (double)(fsf * (float)dy);
+      pz = (double)(fsf * (float)dz);
+      fx += px;
+      fy += py;
+      fz += pz;
+    } else {
+      const double ir = rsqrt_nr(ok ? r2 : 1.0);
+      const double ir2 = ir * ir;
+      const double sr2 = lj.sig2 * ir2;
+      const double sr6 = sr2 * sr2 * sr2;
+      double fs = fma(lj.a24 * ir2 * sr6, fma(2.0, sr6, -1.0), lj.duc * ir);
+      fs = ok ? fs : 0.0;
+      fx = fma(fs, dx, fx);
+      fy = fma(fs, dy, fy);
+      fz = fma(fs, dz, fz);
+      px = fs * dx;
+      py = fs * dy;
+      pz = fs * dz;
+    }
+    if (HALF && ok) {
+      unsafeAtomicAdd(&L.ACC[3 * t + 0], -px);
+      unsafeAtomicAdd(&L.ACC[3 * t + 1], -py);
+      unsafeAtomicAdd(&L.ACC[3 * t + 2], -pz);
+    }
+  });
+}
+
+// Pass 2 for slot s: q_s = sum_t K_st (rho_s - rho_t).
 template <bool F32, bool HALF>
 __device__ __forceinline__ void pass2_slot(const PathArgs& a, const TileLDS& L, const double* R,
                                            const TileScratch& ts, int s, double xs, double ys,
                                            double zs, double rx, double ry, double rz,
                                            double& qx, double& qy, double& qz) {
-  const int N = a.n_atoms;
   const LJConst& lj = a.lj;
   qx = qy = qz = 0.0;
-  const int cnt = ts.cnt[s];
-  auto pair = [&](int t) {
+  for_each_partner<HALF>(a, ts, s, [&](int t, bool valid) {
     const double dx = min_image(xs - L.X[3 * t + 0], lj.box, lj.inv_box);
     const double dy = min_image(ys - L.X[3 * t + 1], lj.box, lj.inv_box);
     const double dz = min_image(zs - L.X[3 * t + 2], lj.box, lj.inv_box);
     const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
-    if (r2 <= lj.rc2) {
-      double kx = 0.0, ky = 0.0, kz = 0.0;
-      PairMath<F32>::accum_hv(lj, dx, dy, dz, r2, rx - R[3 * t + 0], ry - R[3 * t + 1],
-                              rz - R[3 * t + 2], kx, ky, kz);
-      qx += kx;
-      qy += ky;
-      qz += kz;
-      if (HALF) {
-        unsafeAtomicAdd(&L.ACC[3 * t + 0], -kx);
-        unsafeAtomicAdd(&L.ACC[3 * t + 1], -ky);
-        unsafeAtomicAdd(&L.ACC[3 * t + 2], -kz);
-      }
+    const bool ok = valid && r2 <= lj.rc2;
+    const double wx = rx - R[3 * t + 0], wy = ry - R[3 * t + 1], wz = rz - R[3 * t + 2];
+    double kx, ky, kz;
+    if constexpr (F32) {
+      const float ir = rsqrt_f32(ok ? (float)r2 : 1.0f);
+      const float ir2 = ir * ir;
+      const float sr2 = (float)lj.sig2 * ir2;
+      const float sr6 = sr2 * sr2 * sr2;
+      const float c6 = (float)lj.a24 * ir2 * sr6;
+      float av = -fmaf(c6, fmaf(2.0f, sr6, -1.0f), (float)lj.duc * ir);
+      float bv = (c6 * fmaf(26.0f, sr6, -7.0f) - av) * ir2;
+      av = ok ? av : 0.0f;
+      bv = ok ? bv : 0.0f;
+      const float dxf = (float)dx, dyf = (float)dy, dzf = (float)dz;
+      const float wxf = (float)wx, wyf = (float)wy, wzf = (float)wz;
+      const float tt = bv * fmaf(dxf, wxf, fmaf(dyf, wyf, dzf * wzf));
+      kx = (double)fmaf(av, wxf, tt * dxf);
+      ky = (double)fmaf(av, wyf, tt * dyf);
+      kz = (double)fmaf(av, wzf, tt * dzf);
+    } else {
+      const double ir = rsqrt_nr(ok ? r2 : 1.0);
+      const double ir2 = ir * ir;
+      const double sr2 = lj.sig2 * ir2;
+      const double sr6 = sr2 * sr2 * sr2;
+      const double c6 = lj.a24 * ir2 * sr6;
+      double av = -fma(c6, fma(2.0, sr6, -1.0), lj.duc * ir);   // U'(r)/r
+      double bv = (c6 * fma(26.0, sr6, -7.0) - av) * ir2;       // (U'' - U'/r)/r^2
+      av = ok ? av : 0.0;
+      bv = ok ? bv : 0.0;
+      const double tt = bv * fma(dx, wx, fma(dy, wy, dz * wz));
+      kx = fma(av, wx, tt * dx);
+      ky = fma(av, wy, tt * dy);
+      kz = fma(av, wz, tt * dz);
     }
-  };
-  if (cnt >= 0) {
-    const uint16_t* nb = ts.nbr + s;
-#pragma unroll 2
-    for (int k = 0; k < cnt; ++k) pair(nb[(size_t)k * N]);
-  } else {
-    for (int t = 0; t < N; ++t) {
-      if (t == s) continue;
-      if (HALF && !ref_upper(lj, ts.xref, s, t)) continue;
-      pair(t);
+    qx += kx;
+    qy += ky;
+    qz += kz;
+    if (HALF && ok) {
+      unsafeAtomicAdd(&L.ACC[3 * t + 0], -kx);
+      unsafeAtomicAdd(&L.ACC[3 * t + 1], -ky);
+      unsafeAtomicAdd(&L.ACC[3 * t + 2], -kz);
     }
-  }
+  });
 }
 
 template <bool F32, bool RLDS, bool HALF>
