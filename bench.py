@@ -133,6 +133,8 @@ def main(argv=None) -> int:
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--skin", type=float, default=0.0)
     ap.add_argument("--block", type=int, default=0)
+    ap.add_argument("--copy-probe-mb", type=int, default=0,
+                    help="after timing, run one device copy of this many MiB (for counter calibration)")
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the time-sharded "
@@ -197,6 +199,12 @@ def main(argv=None) -> int:
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     kernel_ms = [e.elapsed_ms() for e in events]
+    if args.copy_probe_mb:
+        n = args.copy_probe_mb * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
     for e in events:
         e.close()
     ms_per_step = (t1 - t0) * 1e3 / args.steps

@@ -115,7 +115,7 @@ typedef struct pamd_path {
 } pamd_path;
 
 /* ---- neighbour-list kind (pamd_tuning.neighbour_list) ---- */
-#define PAMD_LIST_AUTO 0          /* half when it fits, else full */
+#define PAMD_LIST_AUTO 0          /* library choice (currently full) */
 #define PAMD_LIST_FULL 1          /* every atom lists all partners; fixed summation order,
                                      results bitwise repeatable run to run */
 #define PAMD_LIST_HALF 2          /* every pair listed once; partner shares added with LDS

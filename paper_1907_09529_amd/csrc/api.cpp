@@ -54,7 +54,7 @@ int fail(int code, const char* fmt, ...) {
 constexpr size_t kLdsMax = 163840;  // LDS per workgroup on gfx950
 constexpr int kMaxGrid = 2048;      // persistent-grid cap: bounds per-block scratch
 constexpr size_t kAlign = 256;
-constexpr double kDefaultSkin = 0.3;  // in units of sigma
+constexpr double kDefaultSkin = 0.45;  // in units of sigma
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
@@ -147,7 +147,7 @@ CellGrid choose_cells(double box, double radius, int n_atoms) {
   const double rho = n_atoms / (box * box * box);
   double best = (double)n_atoms;  // all pairs
   const int cap = std::max(64, 4 * n_atoms);
-  for (int reach = 1; reach <= 2; ++reach) {
+  for (int reach = 1; reach <= 3; ++reach) {
     int nc = (int)std::floor(reach * box / radius);
     while (nc >= 2 * reach + 1 && (int64_t)nc * nc * nc > cap) --nc;
     if (nc < 2 * reach + 1) continue;
@@ -242,7 +242,7 @@ int make_plan(const pamd_path* p, const pamd_potential* v, const pamd_tuning* t_
     P.kmax = (int)align_up((size_t)P.kmax, 8);  // lists are read in chunks of 8
     P.block = t.block ? t.block : (have_cache && cached.block ? cached.block : default_block(N));
     int tile = t.tile ? t.tile : (have_cache && cached.tile ? cached.tile : 0);
-    if (tile <= 0) tile = (int)std::max<int64_t>(1, std::min<int64_t>(32, P.steps / 512));
+    if (tile <= 0) tile = (int)std::max<int64_t>(1, std::min<int64_t>(32, P.steps / 256));
     P.tile = (int)std::min<int64_t>(tile, P.steps);
     P.n_tiles = (int)((P.steps + P.tile - 1) / P.tile);
     P.grid = std::min(P.n_tiles, kMaxGrid);
@@ -252,7 +252,7 @@ int make_plan(const pamd_path* p, const pamd_potential* v, const pamd_tuning* t_
                          fused_lds_bytes(N, P.cells.nc, false, true) <= kLdsMax;
     if (list == PAMD_LIST_HALF && !half_ok)
       return fail(PAMD_EUNSUPPORTED, "half lists need n_atoms <= %d * block and LDS for 2 slice arrays", fused_half_slots());
-    P.half = list == PAMD_LIST_HALF || (list == PAMD_LIST_AUTO && half_ok);
+    P.half = list == PAMD_LIST_HALF;  // automatic choice: full lists (repeatable, as fast)
     const size_t lds_r = fused_lds_bytes(N, P.cells.nc, true, P.half);
     const size_t lds_g = fused_lds_bytes(N, P.cells.nc, false, P.half);
     if (lds_r <= kLdsMax) {

@@ -45,7 +45,7 @@ CellChoice cells_for(double box, double radius, int n_atoms) {
   const double rho = n_atoms / (box * box * box);
   double best = (double)n_atoms;
   const int cap = std::max(64, 4 * n_atoms);
-  for (int reach = 1; reach <= 2; ++reach) {
+  for (int reach = 1; reach <= 3; ++reach) {
     int nc = (int)std::floor(reach * box / radius);
     while (nc >= 2 * reach + 1 && (int64_t)nc * nc * nc > cap) --nc;
     if (nc < 2 * reach + 1) continue;
@@ -126,7 +126,7 @@ int pamd_batch_create(int32_t n_paths, const pamd_path* paths, const pamd_potent
     const pamd_path& P = paths[p];
     const pamd_potential& V = pots[p];
     const int N = P.n_atoms;
-    const double skin = skin_in > 0 ? skin_in : 0.3 * V.sigma;
+    const double skin = skin_in > 0 ? skin_in : 0.45 * V.sigma;
     const double radius = V.rc + skin;
     CellChoice cc = cells_for(V.box, radius, N);
     const double rho = N / (V.box * V.box * V.box);
@@ -201,7 +201,7 @@ int pamd_batch_create(int32_t n_paths, const pamd_path* paths, const pamd_potent
       delete b;
       return batch_fail(PAMD_EUNSUPPORTED, "half lists do not fit this batch");
     }
-    L.half = list == PAMD_LIST_HALF || (list == PAMD_LIST_AUTO && half_ok);
+    L.half = list == PAMD_LIST_HALF;  // automatic choice: full lists
     const size_t lr = L.half ? max_lds_rh : max_lds_r, lg = L.half ? max_lds_gh : max_lds_g;
     if (lr <= kLdsMax) {
       L.r_in_lds = true;

@@ -45,6 +45,18 @@ __device__ __forceinline__ double wave_max(double v) {
   return v;
 }
 
+__device__ __forceinline__ int wave_min_int(int v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v = min(v, __shfl_xor(v, off, WAVE));
+  return v;
+}
+
+__device__ __forceinline__ int wave_max_int(int v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v = max(v, __shfl_xor(v, off, WAVE));
+  return v;
+}
+
 // Block-wide sum; result valid in thread 0 only.  `scratch` holds >= 16 doubles.
 __device__ __forceinline__ double block_sum(double v, double* scratch) {
   v = wave_sum(v);

@@ -123,63 +123,112 @@ __device__ void rebuild(const PathArgs& a, TileLDS& L, const TileScratch& ts, do
     __syncthreads();
   }
   const int nc = a.nc, reach = a.reach;
-  for (int s = threadIdx.x; s < N; s += B) {
-    const double xs = L.X[3 * s], ys = L.X[3 * s + 1], zs = L.X[3 * s + 2];
+  const int lane = threadIdx.x & (WAVE - 1);
+  // Each wave scans, for its 64 consecutive slots, the union of their cell
+  // stencils: the candidate index is wave-uniform (LDS broadcast reads, no
+  // divergent loop bounds); every lane tests the candidate against its atom.
+  for (int base = threadIdx.x - lane; base < N; base += B) {
+    const int s = base + lane;
+    const bool live = s < N;
+    const int sc = live ? s : base;
+    const double xs = L.X[3 * sc], ys = L.X[3 * sc + 1], zs = L.X[3 * sc + 2];
     int cnt = 0;
     bool over = false;
-    uint16_t* nb = ts.nbr + (size_t)s * 8;   // entry k at nb[(k >> 3) * 8 N + (k & 7)]
-    const size_t chunk = (size_t)8 * N;
-    auto visit = [&](int t) {
-      const double dx = min_image(xs - L.X[3 * t + 0], box, ib);
-      const double dy = min_image(ys - L.X[3 * t + 1], box, ib);
-      const double dz = min_image(zs - L.X[3 * t + 2], box, ib);
+    // entry k of slot s lives at nbr[((k >> 3) * N + s) * 8 + (k & 7)]; woff
+    // tracks that offset (32-bit) as entries are appended
+    uint16_t* nb = ts.nbr;
+    const int step8 = 8 * N - 7;
+    int woff = sc * 8;
+    auto test = [&](int t, double tx, double ty, double tz) {
+      const double dx = min_image(xs - tx, box, ib);
+      const double dy = min_image(ys - ty, box, ib);
+      const double dz = min_image(zs - tz, box, ib);
       const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
-      if (r2 <= a.rlist2 && (!HALF || upper_half(dx, dy, dz, s, t))) {
-        if (cnt < a.kmax)
-          nb[(size_t)(cnt >> 3) * chunk + (cnt & 7)] = (uint16_t)t;
-        else
-          over = true;
-        ++cnt;
+      const bool pass =
+          live && t != s && r2 <= a.rlist2 && (!HALF || upper_half(dx, dy, dz, s, t));
+      const bool room = cnt < a.kmax;
+      if (pass && room) nb[woff] = (uint16_t)t;
+      over |= pass && !room;
+      woff += pass ? ((cnt & 7) == 7 ? step8 : 1) : 0;
+      cnt += pass ? 1 : 0;
+    };
+    // candidate range [t0, t1) is wave-uniform: positions are read four at a
+    // time (LDS broadcast) before they are tested
+    auto scan = [&](int t0, int t1) {
+      t0 = __builtin_amdgcn_readfirstlane(t0);
+      t1 = __builtin_amdgcn_readfirstlane(t1);
+      int t = t0;
+      for (; t + 4 <= t1; t += 4) {
+        double px[4], py[4], pz[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          px[u] = L.X[3 * (t + u) + 0];
+          py[u] = L.X[3 * (t + u) + 1];
+          pz[u] = L.X[3 * (t + u) + 2];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) test(t + u, px[u], py[u], pz[u]);
       }
+      for (; t < t1; ++t) test(t, L.X[3 * t], L.X[3 * t + 1], L.X[3 * t + 2]);
     };
     if (nc == 0) {
-      for (int t = 0; t < N; ++t)
-        if (t != s) visit(t);
+      scan(0, N);
     } else {
       const int cx = cell_coord(xs, box, ib, nc);
       const int cy = cell_coord(ys, box, ib, nc);
       const int cz = cell_coord(zs, box, ib, nc);
-      // stencil rows: atoms of cells (x0..x1, y, z) are contiguous slots after
-      // the cell-order sort, so each row is one or two slot ranges
-      for (int oz = -reach; oz <= reach; ++oz) {
-        int z = cz + oz;
-        z += z < 0 ? nc : (z >= nc ? -nc : 0);
-        for (int oy = -reach; oy <= reach; ++oy) {
-          int y = cy + oy;
-          y += y < 0 ? nc : (y >= nc ? -nc : 0);
+      // slots are in z-major cell order, so the wave's z range is contiguous;
+      // y (x) ranges are exact only when the wave lies in one z plane (one row)
+      const int zlo = wave_min_int(live ? cz : nc), zhi = wave_max_int(live ? cz : -1);
+      int ylo = 0, yhi = nc - 1, xlo = 0, xhi = nc - 1;
+      if (zlo == zhi) {
+        ylo = wave_min_int(live ? cy : nc);
+        yhi = wave_max_int(live ? cy : -1);
+        if (ylo == yhi) {
+          xlo = wave_min_int(live ? cx : nc);
+          xhi = wave_max_int(live ? cx : -1);
+        }
+      }
+      // stencil extent per axis (start, count), wrapped periodically
+      auto extent = [&](int l, int h, int& st, int& n) {
+        n = h - l + 1 + 2 * reach;
+        if (n >= nc) {
+          st = 0;
+          n = nc;
+        } else {
+          st = l - reach;
+          st += st < 0 ? nc : 0;
+        }
+      };
+      int zs0, zn, ys0, yn, xs0, xn;
+      extent(zlo, zhi, zs0, zn);
+      extent(ylo, yhi, ys0, yn);
+      extent(xlo, xhi, xs0, xn);
+      for (int iz = 0; iz < zn; ++iz) {
+        int z = zs0 + iz;
+        z -= z >= nc ? nc : 0;
+        for (int iy = 0; iy < yn; ++iy) {
+          int y = ys0 + iy;
+          y -= y >= nc ? nc : 0;
           const int row = (z * nc + y) * nc;
-          const int x0 = cx - reach, x1 = cx + reach;
-          if (x0 >= 0 && x1 < nc) {
-            const int hi = L.cells.start[row + x1 + 1];
-            for (int t = L.cells.start[row + x0]; t < hi; ++t)
-              if (t != s) visit(t);
+          // x cells xs0 .. xs0 + xn - 1 (mod nc) are one or two contiguous slot ranges
+          const int xe = xs0 + xn;
+          if (xe <= nc) {
+            scan(L.cells.start[row + xs0], L.cells.start[row + xe]);
           } else {
-            for (int ox = -reach; ox <= reach; ++ox) {
-              int x = cx + ox;
-              x += x < 0 ? nc : (x >= nc ? -nc : 0);
-              const int hi = L.cells.start[row + x + 1];
-              for (int t = L.cells.start[row + x]; t < hi; ++t)
-                if (t != s) visit(t);
-            }
+            scan(L.cells.start[row + xs0], L.cells.start[row + nc]);
+            scan(L.cells.start[row], L.cells.start[row + xe - nc]);
           }
         }
       }
     }
-    if (!over)  // pad the last chunk with the slot itself (read as invalid)
-      for (int k = cnt; k & 7; ++k) nb[(size_t)(k >> 3) * chunk + (k & 7)] = (uint16_t)s;
-    ts.cnt[s] = over ? -1 : cnt;
+    if (live) {
+      if (!over)  // pad the last chunk with the slot itself (read as invalid)
+        for (int k = cnt; k & 7; ++k) nb[(size_t)(k >> 3) * 8 * N + (size_t)s * 8 + (k & 7)] = (uint16_t)s;
+      ts.cnt[s] = over ? -1 : cnt;
 #pragma unroll
-    for (int c = 0; c < 3; ++c) ts.xref[3 * s + c] = L.X[3 * s + c];
+      for (int c = 0; c < 3; ++c) ts.xref[3 * s + c] = L.X[3 * s + c];
+    }
   }
 }
 
