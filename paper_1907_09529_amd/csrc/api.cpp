@@ -265,7 +265,8 @@ int make_plan(const pamd_path* p, const pamd_potential* v, const pamd_tuning* t_
       return fail(PAMD_EUNSUPPORTED, "n_atoms = %d needs %zu bytes of LDS per workgroup (max %zu)", N, lds_g, kLdsMax);
     }
     P.off_bnd = bump(cur, sizeof(double) * 3 * N * (size_t)std::max(0, P.n_tiles - 1));
-    P.nbr_stride = align_up((size_t)P.kmax * N, 128);
+    // neighbour list, then the exact list; both with one spare chunk per atom
+    P.nbr_stride = 2 * align_up((size_t)(P.kmax + 8) * N, 128);
     P.cnt_stride = align_up((size_t)N, 64);
     P.xref_stride = align_up((size_t)6 * N, 32);
     P.rglob_stride = P.r_in_lds ? 0 : align_up((size_t)3 * N, 32);

@@ -172,7 +172,7 @@ int pamd_batch_create(int32_t n_paths, const pamd_path* paths, const pamd_potent
     max_lds_g = std::max(max_lds_g, fused_lds_bytes(N, cc.nc, false, false));
     max_lds_rh = std::max(max_lds_rh, fused_lds_bytes(N, cc.nc, true, true));
     max_lds_gh = std::max(max_lds_gh, fused_lds_bytes(N, cc.nc, false, true));
-    max_nbr = std::max(max_nbr, (size_t)kmax * N);
+    max_nbr = std::max(max_nbr, (size_t)(kmax + 8) * N);  // one spare chunk per atom
   }
   // Work list: every tile of every member, largest (atoms x steps) first.
   for (int mi = 0; mi < (int)b->members.size(); ++mi) {
@@ -215,7 +215,7 @@ int pamd_batch_create(int32_t n_paths, const pamd_path* paths, const pamd_potent
     }
     L.grid = std::max(1, std::min<int>((int)b->items.size(), kMaxGrid));
   }
-  b->nbr_stride = align_up(max_nbr, 128);
+  b->nbr_stride = 2 * align_up(max_nbr, 128);  // neighbour list + exact list
   b->cnt_stride = align_up((size_t)max_n, 64);
   b->xref_stride = align_up((size_t)6 * max_n, 32);
   b->rglob_stride = L.r_in_lds ? 0 : align_up((size_t)3 * max_n, 32);

@@ -17,7 +17,9 @@
 // itself is exact at every slice.  At every build the atoms are re-sorted in
 // cell order inside LDS, so that threads of a wave handle neighbouring atoms
 // and read largely the same neighbour positions (LDS broadcast, few bank
-// conflicts).
+// conflicts).  Pass 1 records the partners it finds within r_c (the slice's
+// exact list, about 60% of the neighbour list at the default skin), and
+// pass 2 visits only those.
 //
 // Two list kinds:
 //   full  every atom lists all its partners; each pair is evaluated twice and
@@ -25,6 +27,8 @@
 //   half  each pair is listed once (half-space rule on the build-time
 //         displacement); the partner's share is added with LDS float64 atomics
 //         (half the pair arithmetic; sums are order-dependent at rounding level).
+#include <type_traits>
+
 #include "lj_pair.hpp"
 
 namespace pamd {
@@ -38,6 +42,7 @@ struct TileLDS {
   double* red;   // 32 doubles
   int* perm;     // n_atoms: slot -> original atom index
   int* perm2;    // n_atoms: scratch for re-sorting
+  int* ecnt;     // n_atoms: length of the slot's exact list this slice (-1: not recorded)
   CellLDS cells;
 };
 
@@ -58,6 +63,8 @@ __device__ inline TileLDS carve_lds(char* base, int n_atoms, int ncell, bool r_i
   off += sizeof(int) * (size_t)n_atoms;
   t.perm2 = reinterpret_cast<int*>(base + off);
   off += sizeof(int) * (size_t)n_atoms;
+  t.ecnt = reinterpret_cast<int*>(base + off);
+  off += sizeof(int) * (size_t)n_atoms;
   t.cells.tmp = reinterpret_cast<int*>(base + off);
   off += sizeof(int) * 16;
   t.cells.start = reinterpret_cast<int*>(base + off);
@@ -72,7 +79,7 @@ size_t fused_lds_bytes(int n_atoms, int nc, bool r_in_lds, bool half) {
   const size_t ncell = (size_t)nc * nc * nc;
   size_t b = sizeof(double) * 3 * (size_t)n_atoms * (1 + (r_in_lds ? 1 : 0) + (half ? 1 : 0));
   b += sizeof(double) * 32 + sizeof(int) * 16;
-  b += sizeof(int) * 2 * (size_t)n_atoms;
+  b += sizeof(int) * 3 * (size_t)n_atoms;
   b += sizeof(int) * (2 * ncell + 1);
   b += sizeof(int) * (size_t)n_atoms;
   return b;
@@ -84,6 +91,8 @@ int fused_half_slots() { return HALF_SLOTS; }
 // the owning thread touches.
 struct TileScratch {
   uint16_t* nbr;   // kmax (multiple of 8) * n_atoms: chunks of 8 entries, [(k/8) N + s] * 8 + k%8
+  uint16_t* ex;    // same layout: the partners within r_c at the current slice (exact list);
+                   // one spare chunk past kmax takes the stores of rejected entries
   int* cnt;        // n_atoms
   double* xref;    // 3 * n_atoms: positions (sorted slots) at the last list build
   double* rprev;   // 3 * n_atoms: rho_{n-1}, by original atom index
@@ -240,56 +249,76 @@ __device__ __forceinline__ bool ref_upper(const LJConst& lj, const double* xref,
   return upper_half(ux, uy, uz, s, t);
 }
 
-// Visits the list of slot s: chunks of 8 uint16 entries, chunk c at
-// nbr[(c * N + s) * 8]; the next chunk is fetched while the current one is
-// evaluated.  Entries past cnt are padding (the slot itself) and are passed
-// with valid = false.  An overflowed list (cnt < 0) visits every atom of the
-// slot's half (or all atoms with full lists) instead.
-template <bool HALF, typename Pair>
-__device__ __forceinline__ void for_each_partner(const PathArgs& a, const TileScratch& ts, int s,
-                                                 Pair&& pair) {
-  const int N = a.n_atoms;
-  const int cnt = ts.cnt[s];
-  if (cnt >= 0) {
-    const uint4* nb = reinterpret_cast<const uint4*>(ts.nbr) + s;
-    const int nch = (cnt + 7) >> 3;
-    uint4 cur = make_uint4(0u, 0u, 0u, 0u);
-    if (nch > 0) cur = nb[0];
-    for (int ch = 0; ch < nch; ++ch) {
-      uint4 nxt = cur;
-      if (ch + 1 < nch) nxt = nb[(size_t)(ch + 1) * N];
-      const int k0 = ch * 8;
-      const uint32_t w[4] = {cur.x, cur.y, cur.z, cur.w};
+// Decodes the 8 uint16 entries of one list chunk.
+__device__ __forceinline__ int chunk_entry(const uint4& c, int e) {
+  const uint32_t w = e < 2 ? c.x : e < 4 ? c.y : e < 6 ? c.z : c.w;
+  return (int)((w >> (16 * (e & 1))) & 0xffffu);
+}
+
+// Visits a chunked list of slot s (chunk c at list[(c * N + s) * 8]), fetching
+// the next chunk while the current one is evaluated.  Entries past cnt are
+// passed as the slot itself with valid = false.
+template <typename Pair>
+__device__ __forceinline__ void for_each_listed(const uint16_t* list, int N, int s, int cnt,
+                                                Pair&& pair) {
+  const uint4* nb = reinterpret_cast<const uint4*>(list) + s;
+  const int nch = (cnt + 7) >> 3;
+  uint4 cur = make_uint4(0u, 0u, 0u, 0u);
+  if (nch > 0) cur = nb[0];
+  for (int ch = 0; ch < nch; ++ch) {
+    uint4 nxt = cur;
+    if (ch + 1 < nch) nxt = nb[(size_t)(ch + 1) * N];
+    const int k0 = ch * 8;
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const int t = (int)((w[e >> 1] >> (16 * (e & 1))) & 0xffffu);
-        pair(t, k0 + e < cnt);
-      }
-      cur = nxt;
+    for (int e = 0; e < 8; ++e) {
+      const bool valid = k0 + e < cnt;
+      pair(valid ? chunk_entry(cur, e) : s, valid);
     }
-  } else {
-    for (int t = 0; t < N; ++t) {
-      if (t == s) continue;
-      if (HALF && !ref_upper(a.lj, ts.xref, s, t)) continue;
-      pair(t, true);
-    }
+    cur = nxt;
   }
 }
 
-// Pass 1 for slot s: force on s from its list; with half lists the partners'
-// shares are added into ACC.
+// Overflow scan (the list did not fit): every atom of the slot's half, or
+// every other atom with full lists.
+template <bool HALF, typename Pair>
+__device__ __forceinline__ void for_each_atom(const PathArgs& a, const TileScratch& ts, int s,
+                                              Pair&& pair) {
+  for (int t = 0; t < a.n_atoms; ++t) {
+    if (t == s) continue;
+    if (HALF && !ref_upper(a.lj, ts.xref, s, t)) continue;
+    pair(t, true);
+  }
+}
+
+// Pass 1 for slot s: force on s from its neighbour list.  The partners found
+// within r_c are recorded, in list order, as the slot's exact list of this
+// slice (ts.ex, length in L.ecnt[s]) for pass 2; after an overflow scan no
+// exact list is recorded (-1).  With half lists the partners' shares are
+// added into ACC.
 template <bool F32, bool HALF>
 __device__ __forceinline__ void pass1_slot(const PathArgs& a, const TileLDS& L,
                                            const TileScratch& ts, int s, double xs, double ys,
                                            double zs, double& fx, double& fy, double& fz) {
   const LJConst& lj = a.lj;
+  const int N = a.n_atoms;
   fx = fy = fz = 0.0;
-  for_each_partner<HALF>(a, ts, s, [&](int t, bool valid) {
+  uint16_t* ex = ts.ex;
+  const int step8 = 8 * N - 7;
+  int woff = s * 8;  // offset of the next exact entry (same chunked layout as the lists)
+  int ec = 0;
+  auto body = [&](int t, bool valid, auto record) {
     const double dx = min_image(xs - L.X[3 * t + 0], lj.box, lj.inv_box);
     const double dy = min_image(ys - L.X[3 * t + 1], lj.box, lj.inv_box);
     const double dz = min_image(zs - L.X[3 * t + 2], lj.box, lj.inv_box);
     const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
     const bool ok = valid && r2 <= lj.rc2;
+    if constexpr (decltype(record)::value) {
+      // stored unconditionally: a rejected entry is overwritten by the next
+      // accepted one, or lies past the list's length
+      ex[woff] = (uint16_t)t;
+      woff += ok ? ((ec & 7) == 7 ? step8 : 1) : 0;
+      ec += ok ? 1 : 0;
+    }
     double px, py, pz;
     if constexpr (F32) {
       const float ir = rsqrt_f32(ok ? (float)r2 : 1.0f);
@@ -323,10 +352,21 @@ __device__ __forceinline__ void pass1_slot(const PathArgs& a, const TileLDS& L,
       unsafeAtomicAdd(&L.ACC[3 * t + 1], -py);
       unsafeAtomicAdd(&L.ACC[3 * t + 2], -pz);
     }
-  });
+  };
+  const int cnt = ts.cnt[s];
+  if (cnt >= 0) {
+    for_each_listed(ts.nbr, N, s, cnt,
+                    [&](int t, bool valid) { body(t, valid, std::true_type{}); });
+    L.ecnt[s] = ec;
+  } else {
+    for_each_atom<HALF>(a, ts, s, [&](int t, bool valid) { body(t, valid, std::false_type{}); });
+    L.ecnt[s] = -1;
+  }
 }
 
-// Pass 2 for slot s: q_s = sum_t K_st (rho_s - rho_t).
+// Pass 2 for slot s: q_s = sum_t K_st (rho_s - rho_t) over the exact list
+// recorded in pass 1 (no cutoff test: every entry is within r_c at this
+// slice), or over an overflow scan with the cutoff test.
 template <bool F32, bool HALF>
 __device__ __forceinline__ void pass2_slot(const PathArgs& a, const TileLDS& L, const double* R,
                                            const TileScratch& ts, int s, double xs, double ys,
@@ -334,12 +374,13 @@ __device__ __forceinline__ void pass2_slot(const PathArgs& a, const TileLDS& L, 
                                            double& qx, double& qy, double& qz) {
   const LJConst& lj = a.lj;
   qx = qy = qz = 0.0;
-  for_each_partner<HALF>(a, ts, s, [&](int t, bool valid) {
+  auto body = [&](int t, bool valid, auto check) {
     const double dx = min_image(xs - L.X[3 * t + 0], lj.box, lj.inv_box);
     const double dy = min_image(ys - L.X[3 * t + 1], lj.box, lj.inv_box);
     const double dz = min_image(zs - L.X[3 * t + 2], lj.box, lj.inv_box);
     const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
-    const bool ok = valid && r2 <= lj.rc2;
+    bool ok = valid;
+    if constexpr (decltype(check)::value) ok = ok && r2 <= lj.rc2;
     const double wx = rx - R[3 * t + 0], wy = ry - R[3 * t + 1], wz = rz - R[3 * t + 2];
     double kx, ky, kz;
     if constexpr (F32) {
@@ -381,9 +422,14 @@ __device__ __forceinline__ void pass2_slot(const PathArgs& a, const TileLDS& L, 
       unsafeAtomicAdd(&L.ACC[3 * t + 1], -ky);
       unsafeAtomicAdd(&L.ACC[3 * t + 2], -kz);
     }
-  });
+  };
+  const int ec = L.ecnt[s];
+  if (ec >= 0)
+    for_each_listed(ts.ex, a.n_atoms, s, ec,
+                    [&](int t, bool valid) { body(t, valid, std::false_type{}); });
+  else
+    for_each_atom<HALF>(a, ts, s, [&](int t, bool valid) { body(t, valid, std::true_type{}); });
 }
-
 template <bool F32, bool RLDS, bool HALF>
 __device__ void tile_body(const PathArgs& a, int tile, const TileScratch& ts, char* lds_base) {
   const int N = a.n_atoms;
@@ -554,6 +600,7 @@ __device__ void tile_body(const PathArgs& a, int tile, const TileScratch& ts, ch
 __device__ __forceinline__ TileScratch block_scratch(const BlockScratch& s) {
   TileScratch t;
   t.nbr = s.nbr + (size_t)blockIdx.x * s.nbr_stride;
+  t.ex = t.nbr + s.nbr_stride / 2;
   t.cnt = s.cnt + (size_t)blockIdx.x * s.cnt_stride;
   t.xref = s.xref + (size_t)blockIdx.x * s.xref_stride;
   t.rprev = t.xref + s.xref_stride / 2;
