@@ -335,6 +335,7 @@ void fill_lj(const pamd_path* p, const pamd_potential* v, const Plan& P, PathArg
   a.nc = P.cells.nc;
   a.reach = P.cells.reach;
   a.kmax = P.kmax;
+  set_box_units(a);
 }
 
 BlockScratch scratch_of(const Plan& P, void* ws) {

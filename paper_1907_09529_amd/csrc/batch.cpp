@@ -160,6 +160,7 @@ int pamd_batch_create(int32_t n_paths, const pamd_path* paths, const pamd_potent
     a.nc = cc.nc;
     a.reach = cc.reach;
     a.kmax = kmax;
+    set_box_units(a);
     m.x_off = b->x_off[p];
     m.step_off = b->step_off[p];
     m.bnd_off = bnd_elems;

@@ -57,8 +57,10 @@ __device__ __forceinline__ int wave_max_int(int v) {
   return v;
 }
 
-// Block-wide sum; result valid in thread 0 only.  `scratch` holds >= 16 doubles.
-__device__ __forceinline__ double block_sum(double v, double* scratch) {
+// Block-wide sum; result valid in thread 0 only.  `scratch` (LDS, generic or
+// LDS-typed pointer) holds >= 16 doubles.
+template <typename P>
+__device__ __forceinline__ double block_sum(double v, P scratch) {
   v = wave_sum(v);
   const int lane = threadIdx.x & (WAVE - 1);
   const int wid = threadIdx.x / WAVE;
@@ -73,7 +75,8 @@ __device__ __forceinline__ double block_sum(double v, double* scratch) {
 }
 
 // Block-wide max broadcast to every thread.  `scratch` holds >= 17 doubles.
-__device__ __forceinline__ double block_max_all(double v, double* scratch) {
+template <typename P>
+__device__ __forceinline__ double block_max_all(double v, P scratch) {
   v = wave_max(v);
   const int lane = threadIdx.x & (WAVE - 1);
   const int wid = threadIdx.x / WAVE;
@@ -92,7 +95,8 @@ __device__ __forceinline__ double block_max_all(double v, double* scratch) {
 
 // Block-wide exclusive scan of n ints in LDS (in place); writes the total to
 // data[n].  `tmp` holds >= 16 ints.  All threads must call.
-__device__ inline void block_exclusive_scan(int* data, int n, int* tmp) {
+template <typename P>
+__device__ inline void block_exclusive_scan(P data, int n, P tmp) {
   const int nt = blockDim.x;
   const int per = (n + nt - 1) / nt;
   const int lo = threadIdx.x * per;

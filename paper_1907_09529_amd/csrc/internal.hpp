@@ -21,6 +21,17 @@ struct LJConst {
   double duc;        // u'(r_c)
 };
 
+// The same constants in box units (positions u = x / L, displacements du,
+// r^2 = |du|^2), as used by the fused kernel:
+//   force      F += [a24_L p (2 sr6 - 1) + duc iru] du,
+//   Hessian    K w = -fs w + [(a96_L2 p (7 sr6 - 2) + duc_L iru) ir2] (du.w) du,
+// with iru = 1/|du|, ir2 = iru^2, sr6 = (sig2 ir2)^3, p = ir2 sr6 and
+// fs = a24_L2 p (2 sr6 - 1) + duc_L iru (the physical -U'(r)/r).
+struct BoxUnits {
+  double rc2, sig2, rlist2, half_skin2;
+  double a24_L, a24_L2, a96_L2, duc, duc_L, seven;
+};
+
 // One path as seen by the LJ kernels.
 struct PathArgs {
   const double* x;        // (N+1) * 3 * n_atoms
@@ -45,7 +56,25 @@ struct PathArgs {
   int32_t reach;          // stencil half-width in cells
   int32_t kmax;           // list capacity per atom
   int32_t pad0;
+  BoxUnits bu;            // set by set_box_units() from lj, rlist2 and half_skin2
 };
+
+// Fills a.bu from the physical constants.  The list radius is widened by a
+// relative 1e-12 so that rounding in box units can never drop a pair that
+// the physical-unit bound keeps.
+inline void set_box_units(PathArgs& a) {
+  const double ib = a.lj.inv_box, ib2 = ib * ib;
+  a.bu.rc2 = a.lj.rc2 * ib2;
+  a.bu.sig2 = a.lj.sig2 * ib2;
+  a.bu.rlist2 = a.rlist2 * ib2 * (1.0 + 1e-12);
+  a.bu.half_skin2 = a.half_skin2 * ib2;
+  a.bu.a24_L = a.lj.a24 * ib;
+  a.bu.a24_L2 = a.lj.a24 * ib2;
+  a.bu.a96_L2 = 4.0 * a.lj.a24 * ib2;
+  a.bu.duc = a.lj.duc;
+  a.bu.duc_L = a.lj.duc * ib;
+  a.bu.seven = 7.0;
+}
 
 // Per-block scratch in global memory for the fused LJ kernel.
 struct BlockScratch {

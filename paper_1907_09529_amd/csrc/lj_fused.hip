@@ -10,6 +10,11 @@
 // it belongs to the previous tile, which writes c rho_{n0-1} to a boundary
 // buffer that the finalize kernel adds (fixed order, no atomics).
 //
+// Positions in LDS are in box units (u = x / L), so that the minimum image of
+// a displacement is du - rint(du) and the pair terms use constants scaled
+// once on the host (BoxUnits).  Delta_n is taken from the unscaled positions
+// in HBM.
+//
 // Neighbour lists (radius r_c + skin) are built at the tile start from a cell
 // list in LDS and reused while no atom has moved more than skin/2 from where
 // the list was built (then every pair with r <= r_c at the current slice is
@@ -29,59 +34,68 @@
 //         (half the pair arithmetic; sums are order-dependent at rounding level).
 #include <type_traits>
 
-#include "lj_pair.hpp"
+#include "device.hpp"
+#include "internal.hpp"
 
 namespace pamd {
 
+// LDS-typed pointers: 32-bit addressing for every shared-memory access.
+typedef __attribute__((address_space(3))) double lds_f64;
+typedef __attribute__((address_space(3))) int lds_i32;
+
 constexpr int HALF_SLOTS = 2;  // atoms per thread supported by the half-list kernel
 
+// Shared-memory layout of one tile.  With rho in LDS every slot holds 6
+// doubles, its position u (0..2) and rho (3..5), so that pass 2 reads both
+// from one address; otherwise 3 (positions only; rho lives in global scratch).
 struct TileLDS {
-  double* X;     // 3 * n_atoms, slice x_n, sorted slots (AoS)
-  double* R;     // 3 * n_atoms, rho_n, sorted slots (when kept in LDS)
-  double* ACC;   // 3 * n_atoms, partner-share accumulator (half lists)
-  double* red;   // 32 doubles
-  int* perm;     // n_atoms: slot -> original atom index
-  int* perm2;    // n_atoms: scratch for re-sorting
-  int* ecnt;     // n_atoms: length of the slot's exact list this slice (-1: not recorded)
-  CellLDS cells;
+  lds_f64* X;     // stride XS: slice x_n / L, sorted slots
+  lds_f64* ACC;   // 3 * n_atoms, partner-share accumulator (half lists)
+  lds_f64* red;   // 32 doubles
+  lds_i32* perm;  // n_atoms: slot -> original atom index
+  lds_i32* perm2; // n_atoms: scratch for re-sorting
+  lds_i32* ecnt;  // n_atoms: length of the slot's exact list this slice (-1: not recorded)
+  lds_i32* tmp;   // 16
+  lds_i32* start; // ncell + 1: first slot of each cell
+  lds_i32* fill;  // ncell
+  lds_i32* atoms; // n_atoms: slots in cell order
 };
 
-__device__ inline TileLDS carve_lds(char* base, int n_atoms, int ncell, bool r_in_lds,
+__device__ inline TileLDS carve_lds(char* base_generic, int n_atoms, int ncell, bool r_in_lds,
                                     bool half) {
+  typedef __attribute__((address_space(3))) char lds_char;
+  lds_char* base = (lds_char*)base_generic;
   TileLDS t;
-  size_t off = 0;
-  const size_t vec = sizeof(double) * 3 * (size_t)n_atoms;
-  t.X = reinterpret_cast<double*>(base + off);
-  off += vec;
-  t.R = r_in_lds ? reinterpret_cast<double*>(base + off) : nullptr;
-  off += r_in_lds ? vec : 0;
-  t.ACC = half ? reinterpret_cast<double*>(base + off) : nullptr;
-  off += half ? vec : 0;
-  t.red = reinterpret_cast<double*>(base + off);
-  off += sizeof(double) * 32;
-  t.perm = reinterpret_cast<int*>(base + off);
-  off += sizeof(int) * (size_t)n_atoms;
-  t.perm2 = reinterpret_cast<int*>(base + off);
-  off += sizeof(int) * (size_t)n_atoms;
-  t.ecnt = reinterpret_cast<int*>(base + off);
-  off += sizeof(int) * (size_t)n_atoms;
-  t.cells.tmp = reinterpret_cast<int*>(base + off);
-  off += sizeof(int) * 16;
-  t.cells.start = reinterpret_cast<int*>(base + off);
-  off += sizeof(int) * (size_t)(ncell + 1);
-  t.cells.fill = reinterpret_cast<int*>(base + off);
-  off += sizeof(int) * (size_t)ncell;
-  t.cells.atoms = reinterpret_cast<int*>(base + off);
+  uint32_t off = 0;
+  auto f64 = [&](uint32_t n) {
+    lds_f64* p = (lds_f64*)(base + off);
+    off += 8u * n;
+    return p;
+  };
+  auto i32 = [&](uint32_t n) {
+    lds_i32* p = (lds_i32*)(base + off);
+    off += 4u * n;
+    return p;
+  };
+  t.X = f64((r_in_lds ? 6u : 3u) * n_atoms);
+  t.ACC = half ? f64(3u * n_atoms) : nullptr;
+  t.red = f64(32);
+  t.perm = i32(n_atoms);
+  t.perm2 = i32(n_atoms);
+  t.ecnt = i32(n_atoms);
+  t.tmp = i32(16);
+  t.start = i32(ncell + 1);
+  t.fill = i32(ncell);
+  t.atoms = i32(n_atoms);
   return t;
 }
 
 size_t fused_lds_bytes(int n_atoms, int nc, bool r_in_lds, bool half) {
   const size_t ncell = (size_t)nc * nc * nc;
-  size_t b = sizeof(double) * 3 * (size_t)n_atoms * (1 + (r_in_lds ? 1 : 0) + (half ? 1 : 0));
+  size_t b = sizeof(double) * (size_t)n_atoms * ((r_in_lds ? 6 : 3) + (half ? 3 : 0));
   b += sizeof(double) * 32 + sizeof(int) * 16;
-  b += sizeof(int) * 3 * (size_t)n_atoms;
+  b += sizeof(int) * 4 * (size_t)n_atoms;
   b += sizeof(int) * (2 * ncell + 1);
-  b += sizeof(int) * (size_t)n_atoms;
   return b;
 }
 
@@ -90,14 +104,16 @@ int fused_half_slots() { return HALF_SLOTS; }
 // Per-block global scratch for one tile: lists and per-atom state that only
 // the owning thread touches.
 struct TileScratch {
-  uint16_t* nbr;   // kmax (multiple of 8) * n_atoms: chunks of 8 entries, [(k/8) N + s] * 8 + k%8
-  uint16_t* ex;    // same layout: the partners within r_c at the current slice (exact list);
-                   // one spare chunk past kmax takes the stores of rejected entries
+  uint16_t* nbr;   // (kmax + 8) * n_atoms: chunks of 8 entries, [(k/8) N + s] * 8 + k%8
+  uint16_t* ex;    // same layout: the partners within r_c at the current slice (exact list)
   int* cnt;        // n_atoms
-  double* xref;    // 3 * n_atoms: positions (sorted slots) at the last list build
+  double* xref;    // 3 * n_atoms: positions u (sorted slots) at the last list build
   double* rprev;   // 3 * n_atoms: rho_{n-1}, by original atom index
   double* rglob;   // 3 * n_atoms: rho_n (sorted slots) when not in LDS; sort scratch
 };
+
+// Minimum image in box units.
+__device__ __forceinline__ double wrap_u(double du) { return du - __builtin_rint(du); }
 
 // Half-space rule: the pair is stored by the atom whose displacement to its
 // partner points "up" (z, then y, then x); exact ties fall back to slot order.
@@ -108,31 +124,93 @@ __device__ __forceinline__ bool upper_half(double dx, double dy, double dz, int 
   return s < t;
 }
 
+// Cell of a box-unit coordinate: floor(frac(u) nc), clamped.
+__device__ __forceinline__ int cell_of(double u, int nc) {
+  const double w = u - floor(u);
+  const int c = (int)(w * (double)nc);
+  return c < 0 ? 0 : (c >= nc ? nc - 1 : c);
+}
+
+template <int XS>
+__device__ __forceinline__ int cell_of_slot(const lds_f64* X, int s, int nc) {
+  return (cell_of(X[XS * s + 2], nc) * nc + cell_of(X[XS * s + 1], nc)) * nc +
+         cell_of(X[XS * s + 0], nc);
+}
+
+// Counting sort of the slots into nc^3 cells (z-major); members of a cell
+// keep their slot order, so the result does not depend on thread timing.
+template <int XS>
+__device__ void sort_cells(int N, int nc, const TileLDS& L) {
+  const int ncell = nc * nc * nc;
+  const int B = blockDim.x;
+  for (int c = threadIdx.x; c < ncell; c += B) L.start[c] = 0;
+  __syncthreads();
+  for (int s = threadIdx.x; s < N; s += B)
+    atomicAdd((int*)&L.start[cell_of_slot<XS>(L.X, s, nc)], 1);
+  __syncthreads();
+  block_exclusive_scan(L.start, ncell, L.tmp);
+  for (int c = threadIdx.x; c < ncell; c += B) L.fill[c] = L.start[c];
+  __syncthreads();
+  for (int s = threadIdx.x; s < N; s += B)
+    L.atoms[atomicAdd((int*)&L.fill[cell_of_slot<XS>(L.X, s, nc)], 1)] = s;
+  __syncthreads();
+  for (int c = threadIdx.x; c < ncell; c += B) {
+    const int lo = L.start[c], hi = L.start[c + 1];
+    for (int a = lo + 1; a < hi; ++a) {  // insertion sort by slot
+      const int v = L.atoms[a];
+      int b = a - 1;
+      while (b >= lo && L.atoms[b] > v) {
+        L.atoms[b + 1] = L.atoms[b];
+        --b;
+      }
+      L.atoms[b + 1] = v;
+    }
+  }
+  __syncthreads();
+}
+
 // (Re)builds the neighbour lists of the slice in L.X.  With cells, atoms are
 // first re-sorted into cell order (slots and perm are rewritten).
-template <bool HALF>
-__device__ void rebuild(const PathArgs& a, TileLDS& L, const TileScratch& ts, double* tmp) {
+template <int XS, bool HALF>
+__device__ void rebuild(const PathArgs& a, const TileLDS& L, const TileScratch& ts) {
   const int N = a.n_atoms;
   const int B = blockDim.x;
-  const double box = a.lj.box, ib = a.lj.inv_box;
   if (a.nc > 0) {
-    build_cells(a.lj, L.X, N, a.nc, L.cells);
+    sort_cells<XS>(N, a.nc, L);
+    // gather into cell order through scratch: the rho half of each slot
+    // (dead at this point) when rho is in LDS, else global scratch
     for (int s = threadIdx.x; s < N; s += B) {
-      const int old = L.cells.atoms[s];
+      const int old = L.atoms[s];
 #pragma unroll
-      for (int c = 0; c < 3; ++c) tmp[3 * s + c] = L.X[3 * old + c];
+      for (int c = 0; c < 3; ++c) {
+        const double v = L.X[XS * old + c];
+        if constexpr (XS == 6)
+          L.X[XS * s + 3 + c] = v;
+        else
+          ts.rglob[3 * s + c] = v;
+      }
       L.perm2[s] = L.perm[old];
     }
     __syncthreads();
     for (int s = threadIdx.x; s < N; s += B) {
 #pragma unroll
-      for (int c = 0; c < 3; ++c) L.X[3 * s + c] = tmp[3 * s + c];
+      for (int c = 0; c < 3; ++c) {
+        if constexpr (XS == 6)
+          L.X[XS * s + c] = L.X[XS * s + 3 + c];
+        else
+          L.X[XS * s + c] = ts.rglob[3 * s + c];
+      }
       L.perm[s] = L.perm2[s];
     }
     __syncthreads();
   }
   const int nc = a.nc, reach = a.reach;
+  const double rl2 = a.bu.rlist2;
   const int lane = threadIdx.x & (WAVE - 1);
+  // entry k of slot s lives at nbr[((k >> 3) * N + s) * 8 + (k & 7)]; woff
+  // tracks that offset as entries are appended (woff & 7 == k & 7)
+  const uint32_t step8 = 8u * N - 7u;
+  const uint32_t cap = (uint32_t)a.kmax * (uint32_t)N;  // offset span of kmax entries
   // Each wave scans, for its 64 consecutive slots, the union of their cell
   // stencils: the candidate index is wave-uniform (LDS broadcast reads, no
   // divergent loop bounds); every lane tests the candidate against its atom.
@@ -140,26 +218,26 @@ __device__ void rebuild(const PathArgs& a, TileLDS& L, const TileScratch& ts, do
     const int s = base + lane;
     const bool live = s < N;
     const int sc = live ? s : base;
-    const double xs = L.X[3 * sc], ys = L.X[3 * sc + 1], zs = L.X[3 * sc + 2];
-    int cnt = 0;
-    bool over = false;
-    // entry k of slot s lives at nbr[((k >> 3) * N + s) * 8 + (k & 7)]; woff
-    // tracks that offset (32-bit) as entries are appended
+    const double xs = L.X[XS * sc], ys = L.X[XS * sc + 1], zs = L.X[XS * sc + 2];
     uint16_t* nb = ts.nbr;
-    const int step8 = 8 * N - 7;
-    int woff = sc * 8;
+    const uint32_t wbase = 8u * (uint32_t)sc;
+    const uint32_t wcap = wbase + cap;
+    // a lane past the last slot never accepts; its stores go to the spare
+    // chunk of slot sc, which is never read
+    uint32_t woff = live ? wbase : wcap;
+    bool over = false;
     auto test = [&](int t, double tx, double ty, double tz) {
-      const double dx = min_image(xs - tx, box, ib);
-      const double dy = min_image(ys - ty, box, ib);
-      const double dz = min_image(zs - tz, box, ib);
+      const double dx = wrap_u(xs - tx);
+      const double dy = wrap_u(ys - ty);
+      const double dz = wrap_u(zs - tz);
       const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
-      const bool pass =
-          live && t != s && r2 <= a.rlist2 && (!HALF || upper_half(dx, dy, dz, s, t));
-      const bool room = cnt < a.kmax;
-      if (pass && room) nb[woff] = (uint16_t)t;
+      const bool pass = live && t != s && r2 <= rl2 && (!HALF || upper_half(dx, dy, dz, s, t));
+      const bool room = woff < wcap;
+      // stored unconditionally: a rejected candidate is overwritten by the
+      // next accepted one, or lies past the list (at most the spare chunk)
+      nb[woff] = (uint16_t)t;
       over |= pass && !room;
-      woff += pass ? ((cnt & 7) == 7 ? step8 : 1) : 0;
-      cnt += pass ? 1 : 0;
+      woff += (pass && room) ? ((woff & 7u) == 7u ? step8 : 1u) : 0u;
     };
     // candidate range [t0, t1) is wave-uniform: positions are read four at a
     // time (LDS broadcast) before they are tested
@@ -171,21 +249,19 @@ __device__ void rebuild(const PathArgs& a, TileLDS& L, const TileScratch& ts, do
         double px[4], py[4], pz[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-          px[u] = L.X[3 * (t + u) + 0];
-          py[u] = L.X[3 * (t + u) + 1];
-          pz[u] = L.X[3 * (t + u) + 2];
+          px[u] = L.X[XS * (t + u) + 0];
+          py[u] = L.X[XS * (t + u) + 1];
+          pz[u] = L.X[XS * (t + u) + 2];
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u) test(t + u, px[u], py[u], pz[u]);
       }
-      for (; t < t1; ++t) test(t, L.X[3 * t], L.X[3 * t + 1], L.X[3 * t + 2]);
+      for (; t < t1; ++t) test(t, L.X[XS * t], L.X[XS * t + 1], L.X[XS * t + 2]);
     };
     if (nc == 0) {
       scan(0, N);
     } else {
-      const int cx = cell_coord(xs, box, ib, nc);
-      const int cy = cell_coord(ys, box, ib, nc);
-      const int cz = cell_coord(zs, box, ib, nc);
+      const int cx = cell_of(xs, nc), cy = cell_of(ys, nc), cz = cell_of(zs, nc);
       // slots are in z-major cell order, so the wave's z range is contiguous;
       // y (x) ranges are exact only when the wave lies in one z plane (one row)
       const int zlo = wave_min_int(live ? cz : nc), zhi = wave_max_int(live ? cz : -1);
@@ -223,41 +299,41 @@ __device__ void rebuild(const PathArgs& a, TileLDS& L, const TileScratch& ts, do
           // x cells xs0 .. xs0 + xn - 1 (mod nc) are one or two contiguous slot ranges
           const int xe = xs0 + xn;
           if (xe <= nc) {
-            scan(L.cells.start[row + xs0], L.cells.start[row + xe]);
+            scan(L.start[row + xs0], L.start[row + xe]);
           } else {
-            scan(L.cells.start[row + xs0], L.cells.start[row + nc]);
-            scan(L.cells.start[row], L.cells.start[row + xe - nc]);
+            scan(L.start[row + xs0], L.start[row + nc]);
+            scan(L.start[row], L.start[row + xe - nc]);
           }
         }
       }
     }
     if (live) {
-      if (!over)  // pad the last chunk with the slot itself (read as invalid)
-        for (int k = cnt; k & 7; ++k) nb[(size_t)(k >> 3) * 8 * N + (size_t)s * 8 + (k & 7)] = (uint16_t)s;
+      // pad the last chunk with the slot itself (read as invalid)
+      for (uint32_t o = woff; (o & 7u) != 0u; ++o) nb[o] = (uint16_t)s;
+      const uint32_t rel = woff - wbase;
+      const int cnt = (int)((rel & ~7u) / (uint32_t)N + (rel & 7u));
       ts.cnt[s] = over ? -1 : cnt;
 #pragma unroll
-      for (int c = 0; c < 3; ++c) ts.xref[3 * s + c] = L.X[3 * s + c];
+      for (int c = 0; c < 3; ++c) ts.xref[3 * s + c] = L.X[XS * s + c];
     }
   }
 }
 
 // Build-time half-space membership of pair (s, t) for the overflow scan.
-__device__ __forceinline__ bool ref_upper(const LJConst& lj, const double* xref, int s, int t) {
-  const double ux = min_image(xref[3 * s] - xref[3 * t], lj.box, lj.inv_box);
-  const double uy = min_image(xref[3 * s + 1] - xref[3 * t + 1], lj.box, lj.inv_box);
-  const double uz = min_image(xref[3 * s + 2] - xref[3 * t + 2], lj.box, lj.inv_box);
-  return upper_half(ux, uy, uz, s, t);
+__device__ __forceinline__ bool ref_upper(const double* xref, int s, int t) {
+  return upper_half(wrap_u(xref[3 * s] - xref[3 * t]), wrap_u(xref[3 * s + 1] - xref[3 * t + 1]),
+                    wrap_u(xref[3 * s + 2] - xref[3 * t + 2]), s, t);
 }
 
-// Decodes the 8 uint16 entries of one list chunk.
+// Decodes entry e of an 8-entry list chunk.
 __device__ __forceinline__ int chunk_entry(const uint4& c, int e) {
   const uint32_t w = e < 2 ? c.x : e < 4 ? c.y : e < 6 ? c.z : c.w;
   return (int)((w >> (16 * (e & 1))) & 0xffffu);
 }
 
 // Visits a chunked list of slot s (chunk c at list[(c * N + s) * 8]), fetching
-// the next chunk while the current one is evaluated.  Entries past cnt are
-// passed as the slot itself with valid = false.
+// the next chunk while the current one is evaluated.  The last chunk is
+// padded with slot indices; entries past cnt are passed with valid = false.
 template <typename Pair>
 __device__ __forceinline__ void for_each_listed(const uint16_t* list, int N, int s, int cnt,
                                                 Pair&& pair) {
@@ -270,10 +346,7 @@ __device__ __forceinline__ void for_each_listed(const uint16_t* list, int N, int
     if (ch + 1 < nch) nxt = nb[(size_t)(ch + 1) * N];
     const int k0 = ch * 8;
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const bool valid = k0 + e < cnt;
-      pair(valid ? chunk_entry(cur, e) : s, valid);
-    }
+    for (int e = 0; e < 8; ++e) pair(chunk_entry(cur, e), k0 + e < cnt);
     cur = nxt;
   }
 }
@@ -285,142 +358,168 @@ __device__ __forceinline__ void for_each_atom(const PathArgs& a, const TileScrat
                                               Pair&& pair) {
   for (int t = 0; t < a.n_atoms; ++t) {
     if (t == s) continue;
-    if (HALF && !ref_upper(a.lj, ts.xref, s, t)) continue;
+    if (HALF && !ref_upper(ts.xref, s, t)) continue;
     pair(t, true);
   }
 }
 
 // Pass 1 for slot s: force on s from its neighbour list.  The partners found
 // within r_c are recorded, in list order, as the slot's exact list of this
-// slice (ts.ex, length in L.ecnt[s]) for pass 2; after an overflow scan no
-// exact list is recorded (-1).  With half lists the partners' shares are
-// added into ACC.
-template <bool F32, bool HALF>
+// slice (ts.ex, padded with the slot itself to a whole chunk; length in
+// L.ecnt[s]) for pass 2; after an overflow scan no exact list is recorded
+// (-1).  With half lists the partners' shares are added into ACC.
+template <int XS, bool F32, bool HALF>
 __device__ __forceinline__ void pass1_slot(const PathArgs& a, const TileLDS& L,
-                                           const TileScratch& ts, int s, double xs, double ys,
-                                           double zs, double& fx, double& fy, double& fz) {
-  const LJConst& lj = a.lj;
+                                           const TileScratch& ts, int s, double& fx,
+                                           double& fy, double& fz) {
+  const BoxUnits& k = a.bu;
   const int N = a.n_atoms;
+  const double xs = L.X[XS * s], ys = L.X[XS * s + 1], zs = L.X[XS * s + 2];
   fx = fy = fz = 0.0;
   uint16_t* ex = ts.ex;
-  const int step8 = 8 * N - 7;
-  int woff = s * 8;  // offset of the next exact entry (same chunked layout as the lists)
-  int ec = 0;
+  const uint32_t step8 = 8u * N - 7u;
+  const uint32_t wbase = 8u * (uint32_t)s;
+  uint32_t woff = wbase;  // offset of the next exact entry (woff & 7 == count & 7)
   auto body = [&](int t, bool valid, auto record) {
-    const double dx = min_image(xs - L.X[3 * t + 0], lj.box, lj.inv_box);
-    const double dy = min_image(ys - L.X[3 * t + 1], lj.box, lj.inv_box);
-    const double dz = min_image(zs - L.X[3 * t + 2], lj.box, lj.inv_box);
+    const double dx = wrap_u(xs - L.X[XS * t + 0]);
+    const double dy = wrap_u(ys - L.X[XS * t + 1]);
+    const double dz = wrap_u(zs - L.X[XS * t + 2]);
     const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
-    const bool ok = valid && r2 <= lj.rc2;
+    const bool ok = valid && r2 <= k.rc2;
     if constexpr (decltype(record)::value) {
       // stored unconditionally: a rejected entry is overwritten by the next
-      // accepted one, or lies past the list's length
+      // accepted one, or lies past the exact list's length
       ex[woff] = (uint16_t)t;
-      woff += ok ? ((ec & 7) == 7 ? step8 : 1) : 0;
-      ec += ok ? 1 : 0;
+      woff += ok ? ((woff & 7u) == 7u ? step8 : 1u) : 0u;
     }
-    double px, py, pz;
+    // a rejected pair gets iru = 0, which zeroes every term below
+    double px = 0.0, py = 0.0, pz = 0.0;
     if constexpr (F32) {
-      const float ir = rsqrt_f32(ok ? (float)r2 : 1.0f);
-      const float ir2 = ir * ir;
-      const float sr2 = (float)lj.sig2 * ir2;
+      float iru = rsqrt_f32((float)r2);
+      iru = ok ? iru : 0.0f;
+      const float ir2 = iru * iru;
+      const float sr2 = (float)k.sig2 * ir2;
       const float sr6 = sr2 * sr2 * sr2;
-      float fsf = fmaf((float)lj.a24 * ir2 * sr6, fmaf(2.0f, sr6, -1.0f), (float)lj.duc * ir);
-      fsf = ok ? fsf : 0.0f;
-      px = (double)(fsf * (float)dx);
-      py = (double)(fsf * (float)dy);
-      pz = (double)(fsf * (float)dz);
+      const float fsl = fmaf((float)k.a24_L * (ir2 * sr6), fmaf(2.0f, sr6, -1.0f),
+                             (float)k.duc * iru);
+      px = (double)(fsl * (float)dx);
+      py = (double)(fsl * (float)dy);
+      pz = (double)(fsl * (float)dz);
       fx += px;
       fy += py;
       fz += pz;
     } else {
-      const double ir = rsqrt_nr(ok ? r2 : 1.0);
-      const double ir2 = ir * ir;
-      const double sr2 = lj.sig2 * ir2;
+      double iru = rsqrt_nr(r2);
+      iru = ok ? iru : 0.0;
+      const double ir2 = iru * iru;
+      const double sr2 = k.sig2 * ir2;
       const double sr6 = sr2 * sr2 * sr2;
-      double fs = fma(lj.a24 * ir2 * sr6, fma(2.0, sr6, -1.0), lj.duc * ir);
-      fs = ok ? fs : 0.0;
-      fx = fma(fs, dx, fx);
-      fy = fma(fs, dy, fy);
-      fz = fma(fs, dz, fz);
-      px = fs * dx;
-      py = fs * dy;
-      pz = fs * dz;
+      const double fsl = fma(k.a24_L * (ir2 * sr6), fma(2.0, sr6, -1.0), k.duc * iru);
+      fx = fma(fsl, dx, fx);
+      fy = fma(fsl, dy, fy);
+      fz = fma(fsl, dz, fz);
+      if constexpr (HALF) {
+        px = fsl * dx;
+        py = fsl * dy;
+        pz = fsl * dz;
+      }
     }
-    if (HALF && ok) {
-      unsafeAtomicAdd(&L.ACC[3 * t + 0], -px);
-      unsafeAtomicAdd(&L.ACC[3 * t + 1], -py);
-      unsafeAtomicAdd(&L.ACC[3 * t + 2], -pz);
+    if constexpr (HALF) {
+      if (ok) {
+        unsafeAtomicAdd((double*)&L.ACC[3 * t + 0], -px);
+        unsafeAtomicAdd((double*)&L.ACC[3 * t + 1], -py);
+        unsafeAtomicAdd((double*)&L.ACC[3 * t + 2], -pz);
+      }
     }
   };
   const int cnt = ts.cnt[s];
   if (cnt >= 0) {
     for_each_listed(ts.nbr, N, s, cnt,
                     [&](int t, bool valid) { body(t, valid, std::true_type{}); });
-    L.ecnt[s] = ec;
+    for (uint32_t o = woff; (o & 7u) != 0u; ++o) ex[o] = (uint16_t)s;
+    const uint32_t rel = woff - wbase;
+    L.ecnt[s] = (int)((rel & ~7u) / (uint32_t)N + (rel & 7u));
   } else {
     for_each_atom<HALF>(a, ts, s, [&](int t, bool valid) { body(t, valid, std::false_type{}); });
     L.ecnt[s] = -1;
   }
 }
 
-// Pass 2 for slot s: q_s = sum_t K_st (rho_s - rho_t) over the exact list
-// recorded in pass 1 (no cutoff test: every entry is within r_c at this
-// slice), or over an overflow scan with the cutoff test.
-template <bool F32, bool HALF>
-__device__ __forceinline__ void pass2_slot(const PathArgs& a, const TileLDS& L, const double* R,
-                                           const TileScratch& ts, int s, double xs, double ys,
-                                           double zs, double rx, double ry, double rz,
-                                           double& qx, double& qy, double& qz) {
-  const LJConst& lj = a.lj;
+// Pass 2 for slot s: q_s = sum_t K_st (rho_s - rho_t), physical units, from
+// box-unit geometry (see BoxUnits), over the exact list recorded in pass 1
+// (no cutoff test: every entry is within r_c at this slice), or over an
+// overflow scan with the cutoff test.  R holds rho with stride RS.
+template <int XS, int RS, bool F32, bool HALF, typename RPtr>
+__device__ __forceinline__ void pass2_slot(const PathArgs& a, const TileLDS& L, RPtr R,
+                                           const TileScratch& ts, int s, double& qx,
+                                           double& qy, double& qz) {
+  const BoxUnits& k = a.bu;
+  const double xs = L.X[XS * s], ys = L.X[XS * s + 1], zs = L.X[XS * s + 2];
+  const double rx = R[RS * s], ry = R[RS * s + 1], rz = R[RS * s + 2];
   qx = qy = qz = 0.0;
   auto body = [&](int t, bool valid, auto check) {
-    const double dx = min_image(xs - L.X[3 * t + 0], lj.box, lj.inv_box);
-    const double dy = min_image(ys - L.X[3 * t + 1], lj.box, lj.inv_box);
-    const double dz = min_image(zs - L.X[3 * t + 2], lj.box, lj.inv_box);
+    const double dx = wrap_u(xs - L.X[XS * t + 0]);
+    const double dy = wrap_u(ys - L.X[XS * t + 1]);
+    const double dz = wrap_u(zs - L.X[XS * t + 2]);
     const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
     bool ok = valid;
-    if constexpr (decltype(check)::value) ok = ok && r2 <= lj.rc2;
-    const double wx = rx - R[3 * t + 0], wy = ry - R[3 * t + 1], wz = rz - R[3 * t + 2];
-    double kx, ky, kz;
+    if constexpr (decltype(check)::value) ok = ok && r2 <= k.rc2;
+    const double wx = rx - R[RS * t + 0], wy = ry - R[RS * t + 1], wz = rz - R[RS * t + 2];
     if constexpr (F32) {
-      const float ir = rsqrt_f32(ok ? (float)r2 : 1.0f);
-      const float ir2 = ir * ir;
-      const float sr2 = (float)lj.sig2 * ir2;
+      float iru = rsqrt_f32((float)r2);
+      iru = ok ? iru : 0.0f;
+      const float ir2 = iru * iru;
+      const float sr2 = (float)k.sig2 * ir2;
       const float sr6 = sr2 * sr2 * sr2;
-      const float c6 = (float)lj.a24 * ir2 * sr6;
-      float av = -fmaf(c6, fmaf(2.0f, sr6, -1.0f), (float)lj.duc * ir);
-      float bv = (c6 * fmaf(26.0f, sr6, -7.0f) - av) * ir2;
-      av = ok ? av : 0.0f;
-      bv = ok ? bv : 0.0f;
+      const float p = ir2 * sr6;
+      const float ducir = (float)k.duc_L * iru;
+      const float fs = fmaf((float)k.a24_L2 * p, fmaf(2.0f, sr6, -1.0f), ducir);
+      const float bv = fmaf((float)k.a96_L2 * p, fmaf(sr6, 7.0f, -2.0f), ducir) * ir2;
       const float dxf = (float)dx, dyf = (float)dy, dzf = (float)dz;
       const float wxf = (float)wx, wyf = (float)wy, wzf = (float)wz;
       const float tt = bv * fmaf(dxf, wxf, fmaf(dyf, wyf, dzf * wzf));
-      kx = (double)fmaf(av, wxf, tt * dxf);
-      ky = (double)fmaf(av, wyf, tt * dyf);
-      kz = (double)fmaf(av, wzf, tt * dzf);
+      const double kx = (double)fmaf(-fs, wxf, tt * dxf);
+      const double ky = (double)fmaf(-fs, wyf, tt * dyf);
+      const double kz = (double)fmaf(-fs, wzf, tt * dzf);
+      qx += kx;
+      qy += ky;
+      qz += kz;
+      if constexpr (HALF) {
+        if (ok) {
+          unsafeAtomicAdd((double*)&L.ACC[3 * t + 0], -kx);
+          unsafeAtomicAdd((double*)&L.ACC[3 * t + 1], -ky);
+          unsafeAtomicAdd((double*)&L.ACC[3 * t + 2], -kz);
+        }
+      }
     } else {
-      const double ir = rsqrt_nr(ok ? r2 : 1.0);
-      const double ir2 = ir * ir;
-      const double sr2 = lj.sig2 * ir2;
+      double iru = rsqrt_nr(r2);
+      iru = ok ? iru : 0.0;
+      const double ir2 = iru * iru;
+      const double sr2 = k.sig2 * ir2;
       const double sr6 = sr2 * sr2 * sr2;
-      const double c6 = lj.a24 * ir2 * sr6;
-      double av = -fma(c6, fma(2.0, sr6, -1.0), lj.duc * ir);   // U'(r)/r
-      double bv = (c6 * fma(26.0, sr6, -7.0) - av) * ir2;       // (U'' - U'/r)/r^2
-      av = ok ? av : 0.0;
-      bv = ok ? bv : 0.0;
+      const double p = ir2 * sr6;
+      const double ducir = k.duc_L * iru;
+      // fs = -U'(r)/r;  bv = (U'' - U'/r) L^2 / r^2
+      const double fs = fma(k.a24_L2 * p, fma(2.0, sr6, -1.0), ducir);
+      const double bv = fma(k.a96_L2 * p, fma(sr6, k.seven, -2.0), ducir) * ir2;
       const double tt = bv * fma(dx, wx, fma(dy, wy, dz * wz));
-      kx = fma(av, wx, tt * dx);
-      ky = fma(av, wy, tt * dy);
-      kz = fma(av, wz, tt * dz);
-    }
-    qx += kx;
-    qy += ky;
-    qz += kz;
-    if (HALF && ok) {
-      unsafeAtomicAdd(&L.ACC[3 * t + 0], -kx);
-      unsafeAtomicAdd(&L.ACC[3 * t + 1], -ky);
-      unsafeAtomicAdd(&L.ACC[3 * t + 2], -kz);
+      if constexpr (HALF) {
+        const double kx = fma(-fs, wx, tt * dx);
+        const double ky = fma(-fs, wy, tt * dy);
+        const double kz = fma(-fs, wz, tt * dz);
+        qx += kx;
+        qy += ky;
+        qz += kz;
+        if (ok) {
+          unsafeAtomicAdd((double*)&L.ACC[3 * t + 0], -kx);
+          unsafeAtomicAdd((double*)&L.ACC[3 * t + 1], -ky);
+          unsafeAtomicAdd((double*)&L.ACC[3 * t + 2], -kz);
+        }
+      } else {
+        qx = fma(tt, dx, fma(-fs, wx, qx));
+        qy = fma(tt, dy, fma(-fs, wy, qy));
+        qz = fma(tt, dz, fma(-fs, wz, qz));
+      }
     }
   };
   const int ec = L.ecnt[s];
@@ -430,25 +529,38 @@ __device__ __forceinline__ void pass2_slot(const PathArgs& a, const TileLDS& L, 
   else
     for_each_atom<HALF>(a, ts, s, [&](int t, bool valid) { body(t, valid, std::true_type{}); });
 }
+
 template <bool F32, bool RLDS, bool HALF>
 __device__ void tile_body(const PathArgs& a, int tile, const TileScratch& ts, char* lds_base) {
+  constexpr int XS = RLDS ? 6 : 3;  // LDS doubles per slot
   const int N = a.n_atoms;
   const int ncell = a.nc * a.nc * a.nc;
-  TileLDS L = carve_lds(lds_base, N, ncell, RLDS, HALF);
-  double* R = RLDS ? L.R : ts.rglob;
-  double* sort_tmp = RLDS ? L.R : (HALF ? L.ACC : ts.rglob);
+  const TileLDS L = carve_lds(lds_base, N, ncell, RLDS, HALF);
   const int64_t n0 = (int64_t)tile * a.tile;
   const int64_t n1 = min(n0 + (int64_t)a.tile, a.n_steps);
   const size_t slice = (size_t)3 * N;
   const bool grad = (a.mode & MODE_GRAD) != 0;
   const int B = blockDim.x;
   const double box = a.lj.box, ib = a.lj.inv_box;
+  // rho_n of slot s, component c
+  auto rho_get = [&](int s, int c) -> double {
+    if constexpr (RLDS)
+      return L.X[6 * s + 3 + c];
+    else
+      return ts.rglob[3 * s + c];
+  };
+  auto rho_set = [&](int s, int c, double v) {
+    if constexpr (RLDS)
+      L.X[6 * s + 3 + c] = v;
+    else
+      ts.rglob[3 * s + c] = v;
+  };
 
   for (int i = threadIdx.x; i < N; i += B) {
     L.perm[i] = i;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      L.X[3 * i + c] = a.x[(size_t)n0 * slice + (size_t)c * N + i];
+      L.X[XS * i + c] = a.x[(size_t)n0 * slice + (size_t)c * N + i] * ib;
       ts.rprev[3 * i + c] = 0.0;
     }
   }
@@ -456,22 +568,23 @@ __device__ void tile_body(const PathArgs& a, int tile, const TileScratch& ts, ch
 
   for (int64_t n = n0; n < n1; ++n) {
     const double w = a.weights ? a.weights[n] : 1.0;
-    const double* xnext = a.x + (size_t)(n + 1) * slice;
+    const double* xcur = a.x + (size_t)n * slice;
+    const double* xnext = xcur + slice;
     __syncthreads();  // X holds x_n
 
     if (!need_build) {
       double m = 0.0;
       for (int s = threadIdx.x; s < N; s += B) {
-        const double ux = min_image(L.X[3 * s + 0] - ts.xref[3 * s + 0], box, ib);
-        const double uy = min_image(L.X[3 * s + 1] - ts.xref[3 * s + 1], box, ib);
-        const double uz = min_image(L.X[3 * s + 2] - ts.xref[3 * s + 2], box, ib);
+        const double ux = wrap_u(L.X[XS * s + 0] - ts.xref[3 * s + 0]);
+        const double uy = wrap_u(L.X[XS * s + 1] - ts.xref[3 * s + 1]);
+        const double uz = wrap_u(L.X[XS * s + 2] - ts.xref[3 * s + 2]);
         m = fmax(m, fma(ux, ux, fma(uy, uy, uz * uz)));
       }
       m = block_max_all(m, L.red);
-      need_build = !(m <= a.half_skin2);
+      need_build = !(m <= a.bu.half_skin2);
     }
     if (need_build) {
-      rebuild<HALF>(a, L, ts, sort_tmp);
+      rebuild<XS, HALF>(a, L, ts);
       need_build = false;
     }
     if (HALF) {
@@ -481,39 +594,36 @@ __device__ void tile_body(const PathArgs& a, int tile, const TileScratch& ts, ch
 
     // ---- pass 1: force, residual, per-step action ----
     double s_loc = 0.0, e_loc = 0.0;
+    auto residual = [&](int s, const double* f) {
+      const int o = L.perm[s];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const size_t e = (size_t)c * N + o;
+        const double d = min_image(xnext[e] - xcur[e], box, ib);
+        const double r = fma(-a.mu_dt, f[c], d);
+        s_loc = fma(r, r, s_loc);
+        e_loc = fma(r - d, r + d, e_loc);
+        if (grad) rho_set(s, c, w * r);
+      }
+    };
     for (int s = threadIdx.x; s < N; s += B) {
       double f[3];
-      pass1_slot<F32, HALF>(a, L, ts, s, L.X[3 * s], L.X[3 * s + 1], L.X[3 * s + 2], f[0], f[1],
-                            f[2]);
+      pass1_slot<XS, F32, HALF>(a, L, ts, s, f[0], f[1], f[2]);
       if (HALF) {
-        // own partial force waits in R until every partner share has arrived
+        // own partial force waits in rho until every partner share has arrived
 #pragma unroll
-        for (int c = 0; c < 3; ++c) R[3 * s + c] = f[c];
+        for (int c = 0; c < 3; ++c) rho_set(s, c, f[c]);
       } else {
-        const int o = L.perm[s];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          const double d = min_image(xnext[(size_t)c * N + o] - L.X[3 * s + c], box, ib);
-          const double r = fma(-a.mu_dt, f[c], d);
-          s_loc = fma(r, r, s_loc);
-          e_loc = fma(r - d, r + d, e_loc);
-          if (grad) R[3 * s + c] = w * r;
-        }
+        residual(s, f);
       }
     }
     if (HALF) {
       __syncthreads();  // every partner share is in ACC
       for (int s = threadIdx.x; s < N; s += B) {
-        const int o = L.perm[s];
+        double f[3];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          const double f = R[3 * s + c] + L.ACC[3 * s + c];
-          const double d = min_image(xnext[(size_t)c * N + o] - L.X[3 * s + c], box, ib);
-          const double r = fma(-a.mu_dt, f, d);
-          s_loc = fma(r, r, s_loc);
-          e_loc = fma(r - d, r + d, e_loc);
-          R[3 * s + c] = w * r;
-        }
+        for (int c = 0; c < 3; ++c) f[c] = rho_get(s, c) + L.ACC[3 * s + c];
+        residual(s, f);
       }
     }
     const double s_sum = block_sum(s_loc, L.red);
@@ -528,17 +638,21 @@ __device__ void tile_body(const PathArgs& a, int tile, const TileScratch& ts, ch
       if (HALF) {
         for (int e = threadIdx.x; e < 3 * N; e += B) L.ACC[e] = 0.0;
       }
-      __syncthreads();  // R holds rho_n of every atom; ACC cleared
+      __syncthreads();  // rho_n of every atom is stored; ACC cleared
+      const double cq = a.c * a.mu_dt;
       if (!HALF) {
         for (int s = threadIdx.x; s < N; s += B) {
           double q[3];
-          pass2_slot<F32, false>(a, L, R, ts, s, L.X[3 * s], L.X[3 * s + 1], L.X[3 * s + 2],
-                                 R[3 * s], R[3 * s + 1], R[3 * s + 2], q[0], q[1], q[2]);
+          if constexpr (RLDS)
+            pass2_slot<XS, 6, F32, false>(a, L, L.X + 3, ts, s, q[0], q[1], q[2]);
+          else
+            pass2_slot<XS, 3, F32, false>(a, L, (const double*)ts.rglob, ts, s, q[0], q[1],
+                                          q[2]);
           const int o = L.perm[s];
 #pragma unroll
           for (int c = 0; c < 3; ++c) {
-            const double rho = R[3 * s + c];
-            const double g = a.c * (ts.rprev[3 * o + c] - rho + a.mu_dt * q[c]);
+            const double rho = rho_get(s, c);
+            const double g = fma(cq, q[c], a.c * (ts.rprev[3 * o + c] - rho));
             a.grad[(size_t)n * slice + (size_t)c * N + o] = g;
             ts.rprev[3 * o + c] = rho;
           }
@@ -547,25 +661,28 @@ __device__ void tile_body(const PathArgs& a, int tile, const TileScratch& ts, ch
         // own partial q stays in registers until the partner shares arrive
         double q[HALF_SLOTS][3];
 #pragma unroll
-        for (int k = 0; k < HALF_SLOTS; ++k) {
-          const int s = threadIdx.x + k * B;
-          q[k][0] = q[k][1] = q[k][2] = 0.0;
-          if (s < N)
-            pass2_slot<F32, true>(a, L, R, ts, s, L.X[3 * s], L.X[3 * s + 1], L.X[3 * s + 2],
-                                  R[3 * s], R[3 * s + 1], R[3 * s + 2], q[k][0], q[k][1],
-                                  q[k][2]);
+        for (int kk = 0; kk < HALF_SLOTS; ++kk) {
+          const int s = threadIdx.x + kk * B;
+          q[kk][0] = q[kk][1] = q[kk][2] = 0.0;
+          if (s < N) {
+            if constexpr (RLDS)
+              pass2_slot<XS, 6, F32, true>(a, L, L.X + 3, ts, s, q[kk][0], q[kk][1], q[kk][2]);
+            else
+              pass2_slot<XS, 3, F32, true>(a, L, (const double*)ts.rglob, ts, s, q[kk][0],
+                                           q[kk][1], q[kk][2]);
+          }
         }
         __syncthreads();  // every partner share is in ACC
 #pragma unroll
-        for (int k = 0; k < HALF_SLOTS; ++k) {
-          const int s = threadIdx.x + k * B;
+        for (int kk = 0; kk < HALF_SLOTS; ++kk) {
+          const int s = threadIdx.x + kk * B;
           if (s < N) {
             const int o = L.perm[s];
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-              const double rho = R[3 * s + c];
+              const double rho = rho_get(s, c);
               const double g =
-                  a.c * (ts.rprev[3 * o + c] - rho + a.mu_dt * (q[k][c] + L.ACC[3 * s + c]));
+                  fma(cq, q[kk][c] + L.ACC[3 * s + c], a.c * (ts.rprev[3 * o + c] - rho));
               a.grad[(size_t)n * slice + (size_t)c * N + o] = g;
               ts.rprev[3 * o + c] = rho;
             }
@@ -573,11 +690,11 @@ __device__ void tile_body(const PathArgs& a, int tile, const TileScratch& ts, ch
         }
       }
     }
-    __syncthreads();  // every read of X (and R, ACC) for slice n is done
+    __syncthreads();  // every read of X (and rho, ACC) for slice n is done
     for (int s = threadIdx.x; s < N; s += B) {
       const int o = L.perm[s];
 #pragma unroll
-      for (int c = 0; c < 3; ++c) L.X[3 * s + c] = xnext[(size_t)c * N + o];
+      for (int c = 0; c < 3; ++c) L.X[XS * s + c] = xnext[(size_t)c * N + o] * ib;
     }
   }
 
