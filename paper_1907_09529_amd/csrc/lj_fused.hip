@@ -233,9 +233,8 @@ __device__ void rebuild(const PathArgs& a, const TileLDS& L, const TileScratch& 
       const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
       const bool pass = live && t != s && r2 <= rl2 && (!HALF || upper_half(dx, dy, dz, s, t));
       const bool room = woff < wcap;
-      // stored unconditionally: a rejected candidate is overwritten by the
-      // next accepted one, or lies past the list (at most the spare chunk)
-      nb[woff] = (uint16_t)t;
+      // exec-masked store: only accepting lanes take part
+      if (pass && room) nb[woff] = (uint16_t)t;
       over |= pass && !room;
       woff += (pass && room) ? ((woff & 7u) == 7u ? step8 : 1u) : 0u;
     };
@@ -331,23 +330,33 @@ __device__ __forceinline__ int chunk_entry(const uint4& c, int e) {
   return (int)((w >> (16 * (e & 1))) & 0xffffu);
 }
 
-// Visits a chunked list of slot s (chunk c at list[(c * N + s) * 8]), fetching
-// the next chunk while the current one is evaluated.  The last chunk is
-// padded with slot indices; entries past cnt are passed with valid = false.
+// Chunks of a list fetched ahead of use: the chunk loads come from HBM (the
+// lists of all workgroups do not fit in L2), so several are kept in flight.
+#ifndef PAMD_LIST_PREFETCH
+#define PAMD_LIST_PREFETCH 3
+#endif
+constexpr int LIST_PREFETCH = PAMD_LIST_PREFETCH;
+
+// Visits a chunked list of slot s (chunk c at list[(c * N + s) * 8]) with
+// LIST_PREFETCH chunk loads in flight.  The last chunk is padded with slot
+// indices; entries past cnt are passed with valid = false.
 template <typename Pair>
 __device__ __forceinline__ void for_each_listed(const uint16_t* list, int N, int s, int cnt,
                                                 Pair&& pair) {
   const uint4* nb = reinterpret_cast<const uint4*>(list) + s;
   const int nch = (cnt + 7) >> 3;
-  uint4 cur = make_uint4(0u, 0u, 0u, 0u);
-  if (nch > 0) cur = nb[0];
+  uint4 q[LIST_PREFETCH];
+#pragma unroll
+  for (int i = 0; i < LIST_PREFETCH; ++i) q[i] = i < nch ? nb[(size_t)i * N] : make_uint4(0u, 0u, 0u, 0u);
   for (int ch = 0; ch < nch; ++ch) {
-    uint4 nxt = cur;
-    if (ch + 1 < nch) nxt = nb[(size_t)(ch + 1) * N];
+    const uint4 cur = q[0];
+#pragma unroll
+    for (int i = 0; i + 1 < LIST_PREFETCH; ++i) q[i] = q[i + 1];
+    const int ahead = ch + LIST_PREFETCH;
+    q[LIST_PREFETCH - 1] = ahead < nch ? nb[(size_t)ahead * N] : cur;
     const int k0 = ch * 8;
 #pragma unroll
     for (int e = 0; e < 8; ++e) pair(chunk_entry(cur, e), k0 + e < cnt);
-    cur = nxt;
   }
 }
 
@@ -387,8 +396,8 @@ __device__ __forceinline__ void pass1_slot(const PathArgs& a, const TileLDS& L,
     const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
     const bool ok = valid && r2 <= k.rc2;
     if constexpr (decltype(record)::value) {
-      // stored unconditionally: a rejected entry is overwritten by the next
-      // accepted one, or lies past the exact list's length
+      // stored unconditionally (a branch-free loop body): a rejected entry
+      // is overwritten by the next accepted one, or lies past the list end
       ex[woff] = (uint16_t)t;
       woff += ok ? ((woff & 7u) == 7u ? step8 : 1u) : 0u;
     }
