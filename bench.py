@@ -40,6 +40,24 @@ FLOP_HV_PAIR = 59
 FLOP_SLICE_ATOM = 39
 BYTES_SLICE_ATOM = 48       # read x_n (24 B) + write g_n (24 B)
 
+# HBM bytes per launch of lj_fused_kernel on the default workload and tuning,
+# from rocprofv3 FETCH_SIZE / WRITE_SIZE runs scaled by a 512 MiB copy
+# (profiles/lj_fused_lj864x4096.md).  Reported only while the kernel sources
+# still hash to `sha`; any change to them makes `traffic` null until the
+# counters are taken again.
+MEASURED_TRAFFIC = {"sha": "4395c0fa460caec7", "read_bytes": 1.4820e9, "write_bytes": 7.2202e8}
+TRAFFIC_SOURCES = ["paper_1907_09529_amd/csrc/lj_fused.hip", "paper_1907_09529_amd/csrc/device.hpp",
+                   "paper_1907_09529_amd/csrc/internal.hpp"]
+
+
+def kernel_sources_sha() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for rel in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
 
 def pairs_per_atom(X: np.ndarray, box: float, rc: float, n_sample: int = 8) -> float:
     """Mean number of unique pairs within r_c per atom over sampled slices (k-d tree count)."""
@@ -214,8 +232,14 @@ def main(argv=None) -> int:
     ppa = pairs_per_atom(X, w.box, w.cutoff)
     flop_unit = ppa * (FLOP_FORCE_PAIR + FLOP_HV_PAIR) + FLOP_SLICE_ATOM
     achieved = flop_unit * units / (k_ms * 1e-3)
+    traffic = None
+    default_run = (args.variant == "fused" and args.workload == "lj864" and tuning is None
+                   and not args.autotune)
+    if default_run and MEASURED_TRAFFIC["sha"] and MEASURED_TRAFFIC["sha"] == kernel_sources_sha():
+        traffic = MEASURED_TRAFFIC["read_bytes"] + MEASURED_TRAFFIC["write_bytes"]
     roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64_VALU / 1e12,
-            "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VALU, "traffic": None,
+            "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VALU, "traffic": traffic,
+            "traffic_unit": "bytes per launch (HBM read + write)",
             "kernel": "lj_fused_kernel" if args.variant != "plain" else "plain pipeline",
             "kernel_ms": k_ms, "flop_per_slice_atom": flop_unit, "pairs_per_atom": ppa,
             "hbm_algorithmic_GBps": BYTES_SLICE_ATOM * units / (k_ms * 1e-3) / 1e9}
