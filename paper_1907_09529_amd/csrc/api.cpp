@@ -249,12 +249,12 @@ int make_plan(const pamd_path* p, const pamd_potential* v, const pamd_tuning* t_
     int list = t.neighbour_list ? t.neighbour_list
                                 : (have_cache && cached.neighbour_list ? cached.neighbour_list : PAMD_LIST_AUTO);
     const bool half_ok = N <= fused_half_slots() * P.block &&
-                         fused_lds_bytes(N, P.cells.nc, false, true) <= kLdsMax;
+                         fused_lds_bytes(N, P.cells.nc, false, true, P.block) <= kLdsMax;
     if (list == PAMD_LIST_HALF && !half_ok)
       return fail(PAMD_EUNSUPPORTED, "half lists need n_atoms <= %d * block and LDS for 2 slice arrays", fused_half_slots());
     P.half = list == PAMD_LIST_HALF;  // automatic choice: full lists (repeatable, as fast)
-    const size_t lds_r = fused_lds_bytes(N, P.cells.nc, true, P.half);
-    const size_t lds_g = fused_lds_bytes(N, P.cells.nc, false, P.half);
+    const size_t lds_r = fused_lds_bytes(N, P.cells.nc, true, P.half, P.block);
+    const size_t lds_g = fused_lds_bytes(N, P.cells.nc, false, P.half, P.block);
     if (lds_r <= kLdsMax) {
       P.r_in_lds = true;
       P.lds = lds_r;

@@ -169,10 +169,10 @@ int pamd_batch_create(int32_t n_paths, const pamd_path* paths, const pamd_potent
     b->slots.push_back(p);
     b->max_tiles = std::max(b->max_tiles, a.n_tiles);
     max_n = std::max(max_n, N);
-    max_lds_r = std::max(max_lds_r, fused_lds_bytes(N, cc.nc, true, false));
-    max_lds_g = std::max(max_lds_g, fused_lds_bytes(N, cc.nc, false, false));
-    max_lds_rh = std::max(max_lds_rh, fused_lds_bytes(N, cc.nc, true, true));
-    max_lds_gh = std::max(max_lds_gh, fused_lds_bytes(N, cc.nc, false, true));
+    max_lds_r = std::max(max_lds_r, fused_lds_bytes(N, cc.nc, true, false, 0));
+    max_lds_g = std::max(max_lds_g, fused_lds_bytes(N, cc.nc, false, false, 0));
+    max_lds_rh = std::max(max_lds_rh, fused_lds_bytes(N, cc.nc, true, true, 0));
+    max_lds_gh = std::max(max_lds_gh, fused_lds_bytes(N, cc.nc, false, true, 0));
     max_nbr = std::max(max_nbr, (size_t)(kmax + 8) * N);  // one spare chunk per atom
   }
   // Work list: every tile of every member, largest (atoms x steps) first.
@@ -197,6 +197,11 @@ int pamd_batch_create(int32_t n_paths, const pamd_path* paths, const pamd_potent
                                         : (int)align_up((size_t)((max_n + per - 1) / per), 64);
     L.block = std::max(64, std::min(1024, block));
     const int list = tuning ? tuning->neighbour_list : PAMD_LIST_AUTO;
+    const size_t stage = fused_lds_stage_bytes(L.block);
+    max_lds_r += stage;
+    max_lds_g += stage;
+    max_lds_rh += stage;
+    max_lds_gh += stage;
     const bool half_ok = max_n <= fused_half_slots() * L.block && max_lds_gh <= kLdsMax;
     if (list == PAMD_LIST_HALF && !half_ok) {
       delete b;

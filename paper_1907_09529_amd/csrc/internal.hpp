@@ -120,7 +120,10 @@ struct BatchBase {
   int32_t pad0;
 };
 
-size_t fused_lds_bytes(int n_atoms, int nc, bool r_in_lds, bool half);
+// Shared memory of the fused kernel's workgroup: the part that grows with
+// the block size is fused_lds_stage_bytes(block), included in the total.
+size_t fused_lds_bytes(int n_atoms, int nc, bool r_in_lds, bool half, int block);
+size_t fused_lds_stage_bytes(int block);
 int fused_half_slots();
 size_t plain_lds_bytes(int n_atoms, int nc);
 

@@ -42,6 +42,7 @@ namespace pamd {
 // LDS-typed pointers: 32-bit addressing for every shared-memory access.
 typedef __attribute__((address_space(3))) double lds_f64;
 typedef __attribute__((address_space(3))) int lds_i32;
+typedef __attribute__((address_space(3))) uint16_t lds_u16;
 
 constexpr int HALF_SLOTS = 2;  // atoms per thread supported by the half-list kernel
 
@@ -52,6 +53,7 @@ struct TileLDS {
   lds_f64* X;     // stride XS: slice x_n / L, sorted slots
   lds_f64* ACC;   // 3 * n_atoms, partner-share accumulator (half lists)
   lds_f64* red;   // 32 doubles
+  lds_u16* stage; // 16 per thread: ring of exact-list entries not yet stored
   lds_i32* perm;  // n_atoms: slot -> original atom index
   lds_i32* perm2; // n_atoms: scratch for re-sorting
   lds_i32* ecnt;  // n_atoms: length of the slot's exact list this slice (-1: not recorded)
@@ -60,6 +62,9 @@ struct TileLDS {
   lds_i32* fill;  // ncell
   lds_i32* atoms; // n_atoms: slots in cell order
 };
+
+// Shared-memory bytes of one tile (see carve_lds).
+constexpr uint32_t STAGE = 16;  // exact-list staging entries per thread
 
 __device__ inline TileLDS carve_lds(char* base_generic, int n_atoms, int ncell, bool r_in_lds,
                                     bool half) {
@@ -80,6 +85,9 @@ __device__ inline TileLDS carve_lds(char* base_generic, int n_atoms, int ncell, 
   t.X = f64((r_in_lds ? 6u : 3u) * n_atoms);
   t.ACC = half ? f64(3u * n_atoms) : nullptr;
   t.red = f64(32);
+  off = (off + 15u) & ~15u;
+  t.stage = (lds_u16*)(base + off);
+  off += 2u * STAGE * blockDim.x;
   t.perm = i32(n_atoms);
   t.perm2 = i32(n_atoms);
   t.ecnt = i32(n_atoms);
@@ -90,14 +98,16 @@ __device__ inline TileLDS carve_lds(char* base_generic, int n_atoms, int ncell, 
   return t;
 }
 
-size_t fused_lds_bytes(int n_atoms, int nc, bool r_in_lds, bool half) {
+size_t fused_lds_bytes(int n_atoms, int nc, bool r_in_lds, bool half, int block) {
   const size_t ncell = (size_t)nc * nc * nc;
   size_t b = sizeof(double) * (size_t)n_atoms * ((r_in_lds ? 6 : 3) + (half ? 3 : 0));
-  b += sizeof(double) * 32 + sizeof(int) * 16;
+  b += sizeof(double) * 32 + 16 + 2 * STAGE * (size_t)block + sizeof(int) * 16;
   b += sizeof(int) * 4 * (size_t)n_atoms;
   b += sizeof(int) * (2 * ncell + 1);
   return b;
 }
+
+size_t fused_lds_stage_bytes(int block) { return 2 * STAGE * (size_t)block; }
 
 int fused_half_slots() { return HALF_SLOTS; }
 
@@ -338,11 +348,12 @@ __device__ __forceinline__ int chunk_entry(const uint4& c, int e) {
 constexpr int LIST_PREFETCH = PAMD_LIST_PREFETCH;
 
 // Visits a chunked list of slot s (chunk c at list[(c * N + s) * 8]) with
-// LIST_PREFETCH chunk loads in flight.  The last chunk is padded with slot
-// indices; entries past cnt are passed with valid = false.
-template <typename Pair>
+// LIST_PREFETCH chunk loads in flight, calling after_chunk() after each chunk.
+// The last chunk is padded with slot indices; entries past cnt are passed
+// with valid = false.
+template <typename Pair, typename Chunk>
 __device__ __forceinline__ void for_each_listed(const uint16_t* list, int N, int s, int cnt,
-                                                Pair&& pair) {
+                                                Pair&& pair, Chunk&& after_chunk) {
   const uint4* nb = reinterpret_cast<const uint4*>(list) + s;
   const int nch = (cnt + 7) >> 3;
   uint4 q[LIST_PREFETCH];
@@ -357,6 +368,7 @@ __device__ __forceinline__ void for_each_listed(const uint16_t* list, int N, int
     const int k0 = ch * 8;
 #pragma unroll
     for (int e = 0; e < 8; ++e) pair(chunk_entry(cur, e), k0 + e < cnt);
+    after_chunk();
   }
 }
 
@@ -385,10 +397,12 @@ __device__ __forceinline__ void pass1_slot(const PathArgs& a, const TileLDS& L,
   const int N = a.n_atoms;
   const double xs = L.X[XS * s], ys = L.X[XS * s + 1], zs = L.X[XS * s + 2];
   fx = fy = fz = 0.0;
-  uint16_t* ex = ts.ex;
-  const uint32_t step8 = 8u * N - 7u;
-  const uint32_t wbase = 8u * (uint32_t)s;
-  uint32_t woff = wbase;  // offset of the next exact entry (woff & 7 == count & 7)
+  // accepted partners go to a 16-entry ring in LDS (a rejected entry's write
+  // lands on the next free position and is overwritten); whole chunks of 8
+  // are stored to the exact list with one 16-byte store
+  lds_u16* ring = L.stage + STAGE * threadIdx.x;
+  uint4* exr = reinterpret_cast<uint4*>(ts.ex) + s;
+  uint32_t acc = 0, done = 0;  // entries accepted / stored
   auto body = [&](int t, bool valid, auto record) {
     const double dx = wrap_u(xs - L.X[XS * t + 0]);
     const double dy = wrap_u(ys - L.X[XS * t + 1]);
@@ -396,10 +410,8 @@ __device__ __forceinline__ void pass1_slot(const PathArgs& a, const TileLDS& L,
     const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
     const bool ok = valid && r2 <= k.rc2;
     if constexpr (decltype(record)::value) {
-      // stored unconditionally (a branch-free loop body): a rejected entry
-      // is overwritten by the next accepted one, or lies past the list end
-      ex[woff] = (uint16_t)t;
-      woff += ok ? ((woff & 7u) == 7u ? step8 : 1u) : 0u;
+      ring[acc & (STAGE - 1)] = (uint16_t)t;
+      acc += ok ? 1u : 0u;
     }
     // a rejected pair gets iru = 0, which zeroes every term below
     double px = 0.0, py = 0.0, pz = 0.0;
@@ -441,13 +453,25 @@ __device__ __forceinline__ void pass1_slot(const PathArgs& a, const TileLDS& L,
       }
     }
   };
+  // Stores the ring's oldest chunk when it is complete (at most 15 entries
+  // are pending); otherwise the same store goes to the row's spare chunk
+  // (index kmax / 8, never read), which keeps the loop free of branches.
+  const uint32_t spare = (uint32_t)a.kmax >> 3;
+  auto flush = [&](bool full) {
+    const uint32_t c = full ? (done >> 3) : spare;
+    exr[(size_t)c * N] = *(const uint4*)(ring + (done & (STAGE - 1)));
+    done += full ? 8u : 0u;
+  };
   const int cnt = ts.cnt[s];
   if (cnt >= 0) {
-    for_each_listed(ts.nbr, N, s, cnt,
-                    [&](int t, bool valid) { body(t, valid, std::true_type{}); });
-    for (uint32_t o = woff; (o & 7u) != 0u; ++o) ex[o] = (uint16_t)s;
-    const uint32_t rel = woff - wbase;
-    L.ecnt[s] = (int)((rel & ~7u) / (uint32_t)N + (rel & 7u));
+    for_each_listed(
+        ts.nbr, N, s, cnt, [&](int t, bool valid) { body(t, valid, std::true_type{}); },
+        [&]() { flush(acc - done >= 8u); });
+    if (acc > done) {  // pad the last chunk with the slot itself
+      for (uint32_t k = acc; k & 7u; ++k) ring[k & (STAGE - 1)] = (uint16_t)s;
+      flush(true);
+    }
+    L.ecnt[s] = (int)acc;
   } else {
     for_each_atom<HALF>(a, ts, s, [&](int t, bool valid) { body(t, valid, std::false_type{}); });
     L.ecnt[s] = -1;
@@ -533,8 +557,9 @@ __device__ __forceinline__ void pass2_slot(const PathArgs& a, const TileLDS& L, 
   };
   const int ec = L.ecnt[s];
   if (ec >= 0)
-    for_each_listed(ts.ex, a.n_atoms, s, ec,
-                    [&](int t, bool valid) { body(t, valid, std::false_type{}); });
+    for_each_listed(
+        ts.ex, a.n_atoms, s, ec, [&](int t, bool valid) { body(t, valid, std::false_type{}); },
+        [] {});
   else
     for_each_atom<HALF>(a, ts, s, [&](int t, bool valid) { body(t, valid, std::true_type{}); });
 }
