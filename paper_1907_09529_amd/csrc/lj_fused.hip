@@ -236,36 +236,50 @@ __device__ void rebuild(const PathArgs& a, const TileLDS& L, const TileScratch& 
     // chunk of slot sc, which is never read
     uint32_t woff = live ? wbase : wcap;
     bool over = false;
-    auto test = [&](int t, double tx, double ty, double tz) {
-      const double dx = wrap_u(xs - tx);
-      const double dy = wrap_u(ys - ty);
-      const double dz = wrap_u(zs - tz);
-      const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
-      const bool pass = live && t != s && r2 <= rl2 && (!HALF || upper_half(dx, dy, dz, s, t));
+    auto append = [&](int t) {
       const bool room = woff < wcap;
-      // exec-masked store: only accepting lanes take part
-      if (pass && room) nb[woff] = (uint16_t)t;
-      over |= pass && !room;
-      woff += (pass && room) ? ((woff & 7u) == 7u ? step8 : 1u) : 0u;
+      if (room) nb[woff] = (uint16_t)t;
+      over |= !room;
+      woff += room ? ((woff & 7u) == 7u ? step8 : 1u) : 0u;
     };
-    // candidate range [t0, t1) is wave-uniform: positions are read four at a
-    // time (LDS broadcast) before they are tested
+    // Candidates [t0, t1) are wave-uniform (LDS broadcast reads).  They are
+    // tested in groups of up to 32: each lane collects its accepted
+    // candidates in a bit mask, then appends them in a short loop over the
+    // set bits, so the test loop itself has no stores and no branches.
     auto scan = [&](int t0, int t1) {
       t0 = __builtin_amdgcn_readfirstlane(t0);
       t1 = __builtin_amdgcn_readfirstlane(t1);
-      int t = t0;
-      for (; t + 4 <= t1; t += 4) {
-        double px[4], py[4], pz[4];
+      for (int g = t0; g < t1; g += 32) {
+        const int gn = min(32, t1 - g);
+        uint32_t bits = 0;
+        for (int j = 0; j < gn; j += 4) {
+          double px[4], py[4], pz[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          px[u] = L.X[XS * (t + u) + 0];
-          py[u] = L.X[XS * (t + u) + 1];
-          pz[u] = L.X[XS * (t + u) + 2];
+          for (int u = 0; u < 4; ++u) {
+            const int t = min(g + j + u, t1 - 1);
+            px[u] = L.X[XS * t + 0];
+            py[u] = L.X[XS * t + 1];
+            pz[u] = L.X[XS * t + 2];
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int t = g + j + u;
+            const double dx = wrap_u(xs - px[u]);
+            const double dy = wrap_u(ys - py[u]);
+            const double dz = wrap_u(zs - pz[u]);
+            const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+            const bool pass = j + u < gn && t != s && r2 <= rl2 &&
+                              (!HALF || upper_half(dx, dy, dz, s, t));
+            bits |= pass ? (1u << (j + u)) : 0u;
+          }
         }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) test(t + u, px[u], py[u], pz[u]);
+        if (!live) bits = 0;
+        while (bits) {
+          const int j = __builtin_ctz(bits);
+          bits &= bits - 1u;
+          append(g + j);
+        }
       }
-      for (; t < t1; ++t) test(t, L.X[XS * t], L.X[XS * t + 1], L.X[XS * t + 2]);
     };
     if (nc == 0) {
       scan(0, N);
@@ -298,20 +312,33 @@ __device__ void rebuild(const PathArgs& a, const TileLDS& L, const TileScratch& 
       extent(zlo, zhi, zs0, zn);
       extent(ylo, yhi, ys0, yn);
       extent(xlo, xhi, xs0, xn);
-      for (int iz = 0; iz < zn; ++iz) {
-        int z = zs0 + iz;
-        z -= z >= nc ? nc : 0;
-        for (int iy = 0; iy < yn; ++iy) {
-          int y = ys0 + iy;
-          y -= y >= nc ? nc : 0;
-          const int row = (z * nc + y) * nc;
-          // x cells xs0 .. xs0 + xn - 1 (mod nc) are one or two contiguous slot ranges
-          const int xe = xs0 + xn;
-          if (xe <= nc) {
-            scan(L.start[row + xs0], L.start[row + xe]);
+      // cells lo .. lo + n - 1 (mod m) of a run of m consecutive runs of
+      // `unit` cells starting at cell `base` are one or two contiguous slot
+      // ranges
+      auto scan_cells = [&](int base, int unit, int lo, int n, int m) {
+        const int hi = lo + n;
+        if (hi <= m) {
+          scan(L.start[base + lo * unit], L.start[base + hi * unit]);
+        } else {
+          scan(L.start[base + lo * unit], L.start[base + m * unit]);
+          scan(L.start[base], L.start[base + (hi - m) * unit]);
+        }
+      };
+      const int plane = nc * nc;
+      if (xn == nc && yn == nc) {
+        scan_cells(0, plane, zs0, zn, nc);  // whole planes
+      } else {
+        for (int iz = 0; iz < zn; ++iz) {
+          int z = zs0 + iz;
+          z -= z >= nc ? nc : 0;
+          if (xn == nc) {
+            scan_cells(z * plane, nc, ys0, yn, nc);  // whole rows of plane z
           } else {
-            scan(L.start[row + xs0], L.start[row + nc]);
-            scan(L.start[row], L.start[row + xe - nc]);
+            for (int iy = 0; iy < yn; ++iy) {
+              int y = ys0 + iy;
+              y -= y >= nc ? nc : 0;
+              scan_cells((z * nc + y) * nc, 1, xs0, xn, nc);
+            }
           }
         }
       }
