@@ -169,8 +169,10 @@ int default_kmax(double box, double radius, int n_atoms) {
   return std::max(1, std::min(k, n_atoms - 1 > 0 ? n_atoms - 1 : 1));
 }
 
-// One atom per thread up to 1024 atoms, else the fewest atoms per thread.
-int default_block(int n_atoms) {
+// Half lists: one atom per thread up to 1024 atoms, else the fewest atoms
+// per thread.  Full lists: two threads per atom, up to 1024 threads.
+int default_block(int n_atoms, bool half) {
+  if (!half) return std::max(64, std::min(1024, (int)align_up((size_t)2 * n_atoms, 64)));
   int per = (n_atoms + 1023) / 1024;
   int b = (int)align_up((size_t)((n_atoms + per - 1) / per), 64);
   return std::max(64, std::min(1024, b));
@@ -240,14 +242,16 @@ int make_plan(const pamd_path* p, const pamd_potential* v, const pamd_tuning* t_
     P.kmax = t.max_neighbours > 0 ? std::min(t.max_neighbours, std::max(1, N - 1))
                                   : default_kmax(L, radius, N);
     P.kmax = (int)align_up((size_t)P.kmax, 8);  // lists are read in chunks of 8
-    P.block = t.block ? t.block : (have_cache && cached.block ? cached.block : default_block(N));
+    int list = t.neighbour_list ? t.neighbour_list
+                                : (have_cache && cached.neighbour_list ? cached.neighbour_list : PAMD_LIST_AUTO);
+    P.block = t.block ? t.block
+                      : (have_cache && cached.block ? cached.block
+                                                    : default_block(N, list == PAMD_LIST_HALF));
     int tile = t.tile ? t.tile : (have_cache && cached.tile ? cached.tile : 0);
     if (tile <= 0) tile = (int)std::max<int64_t>(1, std::min<int64_t>(32, P.steps / 256));
     P.tile = (int)std::min<int64_t>(tile, P.steps);
     P.n_tiles = (int)((P.steps + P.tile - 1) / P.tile);
     P.grid = std::min(P.n_tiles, kMaxGrid);
-    int list = t.neighbour_list ? t.neighbour_list
-                                : (have_cache && cached.neighbour_list ? cached.neighbour_list : PAMD_LIST_AUTO);
     const bool half_ok = N <= fused_half_slots() * P.block &&
                          fused_lds_bytes(N, P.cells.nc, false, true, P.block) <= kLdsMax;
     if (list == PAMD_LIST_HALF && !half_ok)
@@ -266,7 +270,10 @@ int make_plan(const pamd_path* p, const pamd_potential* v, const pamd_tuning* t_
     }
     P.off_bnd = bump(cur, sizeof(double) * 3 * N * (size_t)std::max(0, P.n_tiles - 1));
     // neighbour list, then the exact list; both with one spare chunk per atom
-    P.nbr_stride = 2 * align_up((size_t)(P.kmax + 8) * N, 128);
+    // neighbour lists ((kmax + 8) per atom) and exact lists (up to two rows
+    // per atom, each with a spare chunk: kmax + 32 per atom); both get the
+    // larger size
+    P.nbr_stride = 2 * align_up((size_t)(P.kmax + 32) * N, 128);
     P.cnt_stride = align_up((size_t)N, 64);
     P.xref_stride = align_up((size_t)6 * N, 32);
     P.rglob_stride = P.r_in_lds ? 0 : align_up((size_t)3 * N, 32);
@@ -575,10 +582,12 @@ int pamd_autotune(const pamd_path* p, const pamd_potential* v, const double* x,
   std::vector<pamd_tuning> cands;
   if (v->kind == PAMD_LJ) {
     const int N = p->n_atoms;
-    std::vector<int> blocks;
-    for (int b : {default_block(N), (int)align_up((size_t)(N + 1) / 2, 64), 256, 512, 1024})
-      if (b >= 64 && b <= 1024 && std::find(blocks.begin(), blocks.end(), b) == blocks.end()) blocks.push_back(b);
-    for (int list : {PAMD_LIST_HALF, PAMD_LIST_FULL})
+    for (int list : {PAMD_LIST_HALF, PAMD_LIST_FULL}) {
+      std::vector<int> blocks;
+      for (int b : {default_block(N, list == PAMD_LIST_HALF), (int)align_up((size_t)(N + 1) / 2, 64),
+                    256, 512, 1024})
+        if (b >= 64 && b <= 1024 && std::find(blocks.begin(), blocks.end(), b) == blocks.end())
+          blocks.push_back(b);
       for (int b : blocks)
         for (int tile : {4, 8, 16, 32})
           for (double skin : {0.2, 0.3, 0.45}) {
@@ -590,6 +599,7 @@ int pamd_autotune(const pamd_path* p, const pamd_potential* v, const double* x,
             c.neighbour_list = list;
             cands.push_back(c);
           }
+    }
   } else {
     cands.push_back(pamd_tuning{});
   }

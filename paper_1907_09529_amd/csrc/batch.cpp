@@ -173,7 +173,7 @@ int pamd_batch_create(int32_t n_paths, const pamd_path* paths, const pamd_potent
     max_lds_g = std::max(max_lds_g, fused_lds_bytes(N, cc.nc, false, false, 0));
     max_lds_rh = std::max(max_lds_rh, fused_lds_bytes(N, cc.nc, true, true, 0));
     max_lds_gh = std::max(max_lds_gh, fused_lds_bytes(N, cc.nc, false, true, 0));
-    max_nbr = std::max(max_nbr, (size_t)(kmax + 8) * N);  // one spare chunk per atom
+    max_nbr = std::max(max_nbr, (size_t)(kmax + 32) * N);  // exact lists: 2 rows, spare chunks
   }
   // Work list: every tile of every member, largest (atoms x steps) first.
   for (int mi = 0; mi < (int)b->members.size(); ++mi) {
@@ -192,11 +192,18 @@ int pamd_batch_create(int32_t n_paths, const pamd_path* paths, const pamd_potent
   FusedLaunch& L = b->launch;
   L.f32 = b->f32;
   if (!b->lj_ids.empty()) {
-    int per = (max_n + 1023) / 1024;
-    int block = tuning && tuning->block ? tuning->block
-                                        : (int)align_up((size_t)((max_n + per - 1) / per), 64);
-    L.block = std::max(64, std::min(1024, block));
     const int list = tuning ? tuning->neighbour_list : PAMD_LIST_AUTO;
+    // full lists: two threads per atom; half lists: one atom per thread
+    int block = 0;
+    if (tuning && tuning->block) {
+      block = tuning->block;
+    } else if (list == PAMD_LIST_HALF) {
+      int per = (max_n + 1023) / 1024;
+      block = (int)align_up((size_t)((max_n + per - 1) / per), 64);
+    } else {
+      block = (int)align_up((size_t)2 * max_n, 64);
+    }
+    L.block = std::max(64, std::min(1024, block));
     const size_t stage = fused_lds_stage_bytes(L.block);
     max_lds_r += stage;
     max_lds_g += stage;

@@ -78,7 +78,7 @@ inline void set_box_units(PathArgs& a) {
 
 // Per-block scratch in global memory for the fused LJ kernel.
 struct BlockScratch {
-  uint16_t* nbr;   // per block: neighbour lists, then exact lists, (kmax + 8) * n_atoms each
+  uint16_t* nbr;   // per block: neighbour lists, then exact lists, (kmax + 32) * n_atoms each
   int32_t* cnt;    // n_atoms per block
   double* xref;    // 6 * n_atoms per block: list-build positions, then rho_{n-1}
   double* rglob;   // 3 * n_atoms per block (residuals when they do not fit in LDS), or null

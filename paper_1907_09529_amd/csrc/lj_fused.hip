@@ -45,6 +45,7 @@ typedef __attribute__((address_space(3))) int lds_i32;
 typedef __attribute__((address_space(3))) uint16_t lds_u16;
 
 constexpr int HALF_SLOTS = 2;  // atoms per thread supported by the half-list kernel
+constexpr int EX_PAD = 32;     // exact-list entries per atom beyond kmax (see TileScratch)
 
 // Shared-memory layout of one tile.  With rho in LDS every slot holds 6
 // doubles, its position u (0..2) and rho (3..5), so that pass 2 reads both
@@ -56,7 +57,7 @@ struct TileLDS {
   lds_u16* stage; // 16 per thread: ring of exact-list entries not yet stored
   lds_i32* perm;  // n_atoms: slot -> original atom index
   lds_i32* perm2; // n_atoms: scratch for re-sorting
-  lds_i32* ecnt;  // n_atoms: length of the slot's exact list this slice (-1: not recorded)
+  lds_i32* ecnt;  // 2 n_atoms: exact-list lengths this slice (-1: not recorded)
   lds_i32* tmp;   // 16
   lds_i32* start; // ncell + 1: first slot of each cell
   lds_i32* fill;  // ncell
@@ -90,7 +91,7 @@ __device__ inline TileLDS carve_lds(char* base_generic, int n_atoms, int ncell, 
   off += 2u * STAGE * blockDim.x;
   t.perm = i32(n_atoms);
   t.perm2 = i32(n_atoms);
-  t.ecnt = i32(n_atoms);
+  t.ecnt = i32(2u * n_atoms);
   t.tmp = i32(16);
   t.start = i32(ncell + 1);
   t.fill = i32(ncell);
@@ -102,7 +103,7 @@ size_t fused_lds_bytes(int n_atoms, int nc, bool r_in_lds, bool half, int block)
   const size_t ncell = (size_t)nc * nc * nc;
   size_t b = sizeof(double) * (size_t)n_atoms * ((r_in_lds ? 6 : 3) + (half ? 3 : 0));
   b += sizeof(double) * 32 + 16 + 2 * STAGE * (size_t)block + sizeof(int) * 16;
-  b += sizeof(int) * 4 * (size_t)n_atoms;
+  b += sizeof(int) * 5 * (size_t)n_atoms;
   b += sizeof(int) * (2 * ncell + 1);
   return b;
 }
@@ -114,7 +115,7 @@ int fused_half_slots() { return HALF_SLOTS; }
 // Per-block global scratch for one tile: lists and per-atom state that only
 // the owning thread touches.
 struct TileScratch {
-  uint16_t* nbr;   // (kmax + 8) * n_atoms: chunks of 8 entries, [(k/8) N + s] * 8 + k%8
+  uint16_t* nbr;   // (kmax + EX_PAD) * n_atoms: chunks of 8 entries, [(k/8) N + s] * 8 + k%8
   uint16_t* ex;    // same layout: the partners within r_c at the current slice (exact list)
   int* cnt;        // n_atoms
   double* xref;    // 3 * n_atoms: positions u (sorted slots) at the last list build
@@ -370,28 +371,31 @@ __device__ __forceinline__ int chunk_entry(const uint4& c, int e) {
 // Chunks of a list fetched ahead of use: the chunk loads come from HBM (the
 // lists of all workgroups do not fit in L2), so several are kept in flight.
 #ifndef PAMD_LIST_PREFETCH
-#define PAMD_LIST_PREFETCH 3
+#define PAMD_LIST_PREFETCH 2
 #endif
 constexpr int LIST_PREFETCH = PAMD_LIST_PREFETCH;
 
-// Visits a chunked list of slot s (chunk c at list[(c * N + s) * 8]) with
-// LIST_PREFETCH chunk loads in flight, calling after_chunk() after each chunk.
-// The last chunk is padded with slot indices; entries past cnt are passed
-// with valid = false.
-template <typename Pair, typename Chunk>
-__device__ __forceinline__ void for_each_listed(const uint16_t* list, int N, int s, int cnt,
-                                                Pair&& pair, Chunk&& after_chunk) {
-  const uint4* nb = reinterpret_cast<const uint4*>(list) + s;
+// Visits chunks first, first + STEP, ... of row `row` of a chunked list
+// (chunk c at list[(c * rows + row) * 8]) with LIST_PREFETCH chunk loads in
+// flight, calling after_chunk() after each chunk.  The row's last chunk is
+// padded with slot indices; entries past cnt are passed with valid = false.
+template <int STEP, typename Pair, typename Chunk>
+__device__ __forceinline__ void for_each_listed(const uint16_t* list, int rows, int row, int cnt,
+                                                int first, Pair&& pair, Chunk&& after_chunk) {
+  const uint4* nb = reinterpret_cast<const uint4*>(list) + row;
   const int nch = (cnt + 7) >> 3;
   uint4 q[LIST_PREFETCH];
 #pragma unroll
-  for (int i = 0; i < LIST_PREFETCH; ++i) q[i] = i < nch ? nb[(size_t)i * N] : make_uint4(0u, 0u, 0u, 0u);
-  for (int ch = 0; ch < nch; ++ch) {
+  for (int i = 0; i < LIST_PREFETCH; ++i) {
+    const int c = first + i * STEP;
+    q[i] = c < nch ? nb[(size_t)c * rows] : make_uint4(0u, 0u, 0u, 0u);
+  }
+  for (int ch = first; ch < nch; ch += STEP) {
     const uint4 cur = q[0];
 #pragma unroll
     for (int i = 0; i + 1 < LIST_PREFETCH; ++i) q[i] = q[i + 1];
-    const int ahead = ch + LIST_PREFETCH;
-    q[LIST_PREFETCH - 1] = ahead < nch ? nb[(size_t)ahead * N] : cur;
+    const int ahead = ch + LIST_PREFETCH * STEP;
+    q[LIST_PREFETCH - 1] = ahead < nch ? nb[(size_t)ahead * rows] : cur;
     const int k0 = ch * 8;
 #pragma unroll
     for (int e = 0; e < 8; ++e) pair(chunk_entry(cur, e), k0 + e < cnt);
@@ -399,27 +403,28 @@ __device__ __forceinline__ void for_each_listed(const uint16_t* list, int N, int
   }
 }
 
-// Overflow scan (the list did not fit): every atom of the slot's half, or
-// every other atom with full lists.
-template <bool HALF, typename Pair>
+// Overflow scan (the list did not fit): atoms first, first + STEP, ... of the
+// slot's half (half lists) or of all other atoms (full lists).
+template <bool HALF, int STEP, typename Pair>
 __device__ __forceinline__ void for_each_atom(const PathArgs& a, const TileScratch& ts, int s,
-                                              Pair&& pair) {
-  for (int t = 0; t < a.n_atoms; ++t) {
+                                              int first, Pair&& pair) {
+  for (int t = first; t < a.n_atoms; t += STEP) {
     if (t == s) continue;
     if (HALF && !ref_upper(ts.xref, s, t)) continue;
     pair(t, true);
   }
 }
 
-// Pass 1 for slot s: force on s from its neighbour list.  The partners found
-// within r_c are recorded, in list order, as the slot's exact list of this
-// slice (ts.ex, padded with the slot itself to a whole chunk; length in
-// L.ecnt[s]) for pass 2; after an overflow scan no exact list is recorded
-// (-1).  With half lists the partners' shares are added into ACC.
-template <int XS, bool F32, bool HALF>
-__device__ __forceinline__ void pass1_slot(const PathArgs& a, const TileLDS& L,
-                                           const TileScratch& ts, int s, double& fx,
-                                           double& fy, double& fz) {
+// Pass 1 for slot s, part `part` of STEP: the force on s from neighbour-list
+// chunks part, part + STEP, ... (the caller adds the STEP partial forces).
+// The partners found within r_c are recorded, in list order, as exact-list
+// row `er` of `erows` (ts.ex, padded with the slot itself to a whole chunk;
+// length in L.ecnt[er]) for pass 2; after an overflow scan no exact list is
+// recorded (-1).  With half lists the partners' shares are added into ACC.
+template <int XS, bool F32, bool HALF, int STEP>
+__device__ __forceinline__ void pass1_part(const PathArgs& a, const TileLDS& L,
+                                           const TileScratch& ts, int s, int part, int er,
+                                           int erows, double& fx, double& fy, double& fz) {
   const BoxUnits& k = a.bu;
   const int N = a.n_atoms;
   const double xs = L.X[XS * s], ys = L.X[XS * s + 1], zs = L.X[XS * s + 2];
@@ -428,7 +433,7 @@ __device__ __forceinline__ void pass1_slot(const PathArgs& a, const TileLDS& L,
   // lands on the next free position and is overwritten); whole chunks of 8
   // are stored to the exact list with one 16-byte store
   lds_u16* ring = L.stage + STAGE * threadIdx.x;
-  uint4* exr = reinterpret_cast<uint4*>(ts.ex) + s;
+  uint4* exr = reinterpret_cast<uint4*>(ts.ex) + er;
   uint32_t acc = 0, done = 0;  // entries accepted / stored
   auto body = [&](int t, bool valid, auto record) {
     const double dx = wrap_u(xs - L.X[XS * t + 0]);
@@ -481,38 +486,40 @@ __device__ __forceinline__ void pass1_slot(const PathArgs& a, const TileLDS& L,
     }
   };
   // Stores the ring's oldest chunk when it is complete (at most 15 entries
-  // are pending); otherwise the same store goes to the row's spare chunk
-  // (index kmax / 8, never read), which keeps the loop free of branches.
-  const uint32_t spare = (uint32_t)a.kmax >> 3;
+  // are pending); otherwise the same store goes to the row's last (spare)
+  // chunk, never read, which keeps the loop free of branches.
+  const uint32_t spare = (uint32_t)(a.kmax + EX_PAD) / (8u * STEP) - 1u;  // erows = STEP * N
   auto flush = [&](bool full) {
     const uint32_t c = full ? (done >> 3) : spare;
-    exr[(size_t)c * N] = *(const uint4*)(ring + (done & (STAGE - 1)));
+    exr[(size_t)c * erows] = *(const uint4*)(ring + (done & (STAGE - 1)));
     done += full ? 8u : 0u;
   };
   const int cnt = ts.cnt[s];
   if (cnt >= 0) {
-    for_each_listed(
-        ts.nbr, N, s, cnt, [&](int t, bool valid) { body(t, valid, std::true_type{}); },
+    for_each_listed<STEP>(
+        ts.nbr, N, s, cnt, part, [&](int t, bool valid) { body(t, valid, std::true_type{}); },
         [&]() { flush(acc - done >= 8u); });
     if (acc > done) {  // pad the last chunk with the slot itself
       for (uint32_t k = acc; k & 7u; ++k) ring[k & (STAGE - 1)] = (uint16_t)s;
       flush(true);
     }
-    L.ecnt[s] = (int)acc;
+    L.ecnt[er] = (int)acc;
   } else {
-    for_each_atom<HALF>(a, ts, s, [&](int t, bool valid) { body(t, valid, std::false_type{}); });
-    L.ecnt[s] = -1;
+    for_each_atom<HALF, STEP>(a, ts, s, part,
+                              [&](int t, bool valid) { body(t, valid, std::false_type{}); });
+    L.ecnt[er] = -1;
   }
 }
 
-// Pass 2 for slot s: q_s = sum_t K_st (rho_s - rho_t), physical units, from
-// box-unit geometry (see BoxUnits), over the exact list recorded in pass 1
-// (no cutoff test: every entry is within r_c at this slice), or over an
+// Pass 2 for slot s, part `part` of STEP: q_s = sum_t K_st (rho_s - rho_t),
+// physical units, from box-unit geometry (see BoxUnits), over exact-list row
+// `er` of `erows` recorded by the same part in pass 1 (no cutoff test: every
+// entry is within r_c at this slice), or over the part's share of an
 // overflow scan with the cutoff test.  R holds rho with stride RS.
-template <int XS, int RS, bool F32, bool HALF, typename RPtr>
-__device__ __forceinline__ void pass2_slot(const PathArgs& a, const TileLDS& L, RPtr R,
-                                           const TileScratch& ts, int s, double& qx,
-                                           double& qy, double& qz) {
+template <int XS, int RS, bool F32, bool HALF, int STEP, typename RPtr>
+__device__ __forceinline__ void pass2_part(const PathArgs& a, const TileLDS& L, RPtr R,
+                                           const TileScratch& ts, int s, int part, int er,
+                                           int erows, double& qx, double& qy, double& qz) {
   const BoxUnits& k = a.bu;
   const double xs = L.X[XS * s], ys = L.X[XS * s + 1], zs = L.X[XS * s + 2];
   const double rx = R[RS * s], ry = R[RS * s + 1], rz = R[RS * s + 2];
@@ -582,13 +589,14 @@ __device__ __forceinline__ void pass2_slot(const PathArgs& a, const TileLDS& L, 
       }
     }
   };
-  const int ec = L.ecnt[s];
+  const int ec = L.ecnt[er];
   if (ec >= 0)
-    for_each_listed(
-        ts.ex, a.n_atoms, s, ec, [&](int t, bool valid) { body(t, valid, std::false_type{}); },
+    for_each_listed<1>(
+        ts.ex, erows, er, ec, 0, [&](int t, bool valid) { body(t, valid, std::false_type{}); },
         [] {});
   else
-    for_each_atom<HALF>(a, ts, s, [&](int t, bool valid) { body(t, valid, std::true_type{}); });
+    for_each_atom<HALF, STEP>(a, ts, s, part,
+                              [&](int t, bool valid) { body(t, valid, std::true_type{}); });
 }
 
 template <bool F32, bool RLDS, bool HALF>
@@ -602,6 +610,9 @@ __device__ void tile_body(const PathArgs& a, int tile, const TileScratch& ts, ch
   const size_t slice = (size_t)3 * N;
   const bool grad = (a.mode & MODE_GRAD) != 0;
   const int B = blockDim.x;
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int part = lane >> 5;  // list part of this lane (full lists)
+  const int wv = threadIdx.x / WAVE, nwv = B / WAVE;
   const double box = a.lj.box, ib = a.lj.inv_box;
   // rho_n of slot s, component c
   auto rho_get = [&](int s, int c) -> double {
@@ -667,18 +678,28 @@ __device__ void tile_body(const PathArgs& a, int tile, const TileScratch& ts, ch
         if (grad) rho_set(s, c, w * r);
       }
     };
-    for (int s = threadIdx.x; s < N; s += B) {
-      double f[3];
-      pass1_slot<XS, F32, HALF>(a, L, ts, s, f[0], f[1], f[2]);
-      if (HALF) {
+    if constexpr (!HALF) {
+      // two lanes per atom (lanes l and l + 32 of a wave), each taking every
+      // other list chunk: the block's work comes in half-atom pieces that
+      // spread evenly over the four SIMDs
+      for (int base = wv * 32; base < N; base += nwv * 32) {
+        const int s = base + (lane & 31);
+        const bool live = s < N;
+        double f[3] = {0.0, 0.0, 0.0};
+        if (live)
+          pass1_part<XS, F32, false, 2>(a, L, ts, s, part, 2 * s + part, 2 * N, f[0], f[1], f[2]);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) f[c] += __shfl_xor(f[c], 32, WAVE);
+        if (live && part == 0) residual(s, f);
+      }
+    } else {
+      for (int s = threadIdx.x; s < N; s += B) {
+        double f[3];
+        pass1_part<XS, F32, true, 1>(a, L, ts, s, 0, s, N, f[0], f[1], f[2]);
         // own partial force waits in rho until every partner share has arrived
 #pragma unroll
         for (int c = 0; c < 3; ++c) rho_set(s, c, f[c]);
-      } else {
-        residual(s, f);
       }
-    }
-    if (HALF) {
       __syncthreads();  // every partner share is in ACC
       for (int s = threadIdx.x; s < N; s += B) {
         double f[3];
@@ -701,21 +722,30 @@ __device__ void tile_body(const PathArgs& a, int tile, const TileScratch& ts, ch
       }
       __syncthreads();  // rho_n of every atom is stored; ACC cleared
       const double cq = a.c * a.mu_dt;
-      if (!HALF) {
-        for (int s = threadIdx.x; s < N; s += B) {
-          double q[3];
-          if constexpr (RLDS)
-            pass2_slot<XS, 6, F32, false>(a, L, L.X + 3, ts, s, q[0], q[1], q[2]);
-          else
-            pass2_slot<XS, 3, F32, false>(a, L, (const double*)ts.rglob, ts, s, q[0], q[1],
-                                          q[2]);
-          const int o = L.perm[s];
+      if constexpr (!HALF) {
+        for (int base = wv * 32; base < N; base += nwv * 32) {
+          const int s = base + (lane & 31);
+          const bool live = s < N;
+          double q[3] = {0.0, 0.0, 0.0};
+          if (live) {
+            if constexpr (RLDS)
+              pass2_part<XS, 6, F32, false, 2>(a, L, L.X + 3, ts, s, part, 2 * s + part, 2 * N,
+                                               q[0], q[1], q[2]);
+            else
+              pass2_part<XS, 3, F32, false, 2>(a, L, (const double*)ts.rglob, ts, s, part,
+                                               2 * s + part, 2 * N, q[0], q[1], q[2]);
+          }
 #pragma unroll
-          for (int c = 0; c < 3; ++c) {
-            const double rho = rho_get(s, c);
-            const double g = fma(cq, q[c], a.c * (ts.rprev[3 * o + c] - rho));
-            a.grad[(size_t)n * slice + (size_t)c * N + o] = g;
-            ts.rprev[3 * o + c] = rho;
+          for (int c = 0; c < 3; ++c) q[c] += __shfl_xor(q[c], 32, WAVE);
+          if (live && part == 0) {
+            const int o = L.perm[s];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+              const double rho = rho_get(s, c);
+              const double g = fma(cq, q[c], a.c * (ts.rprev[3 * o + c] - rho));
+              a.grad[(size_t)n * slice + (size_t)c * N + o] = g;
+              ts.rprev[3 * o + c] = rho;
+            }
           }
         }
       } else {
@@ -727,10 +757,11 @@ __device__ void tile_body(const PathArgs& a, int tile, const TileScratch& ts, ch
           q[kk][0] = q[kk][1] = q[kk][2] = 0.0;
           if (s < N) {
             if constexpr (RLDS)
-              pass2_slot<XS, 6, F32, true>(a, L, L.X + 3, ts, s, q[kk][0], q[kk][1], q[kk][2]);
+              pass2_part<XS, 6, F32, true, 1>(a, L, L.X + 3, ts, s, 0, s, N, q[kk][0], q[kk][1],
+                                              q[kk][2]);
             else
-              pass2_slot<XS, 3, F32, true>(a, L, (const double*)ts.rglob, ts, s, q[kk][0],
-                                           q[kk][1], q[kk][2]);
+              pass2_part<XS, 3, F32, true, 1>(a, L, (const double*)ts.rglob, ts, s, 0, s, N,
+                                              q[kk][0], q[kk][1], q[kk][2]);
           }
         }
         __syncthreads();  // every partner share is in ACC
