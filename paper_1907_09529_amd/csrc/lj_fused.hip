@@ -362,11 +362,29 @@ __device__ __forceinline__ bool ref_upper(const double* xref, int s, int t) {
                     wrap_u(xref[3 * s + 2] - xref[3 * t + 2]), s, t);
 }
 
-// Decodes entry e of an 8-entry list chunk.
-__device__ __forceinline__ int chunk_entry(const uint4& c, int e) {
-  const uint32_t w = e < 2 ? c.x : e < 4 ? c.y : e < 6 ? c.z : c.w;
-  return (int)((w >> (16 * (e & 1))) & 0xffffu);
-}
+// List chunks: CH uint16 entries read with one load (neighbour lists: 8,
+// exact lists: 4, which halves the padding of their shorter rows).
+template <int CH>
+struct ChunkOf;
+template <>
+struct ChunkOf<8> {
+  typedef uint4 T;
+  static __device__ __forceinline__ T zero() { return make_uint4(0u, 0u, 0u, 0u); }
+  static __device__ __forceinline__ int entry(const T& c, int e) {
+    const uint32_t w = e < 2 ? c.x : e < 4 ? c.y : e < 6 ? c.z : c.w;
+    return (int)((w >> (16 * (e & 1))) & 0xffffu);
+  }
+};
+template <>
+struct ChunkOf<4> {
+  typedef uint2 T;
+  static __device__ __forceinline__ T zero() { return make_uint2(0u, 0u); }
+  static __device__ __forceinline__ int entry(const T& c, int e) {
+    const uint32_t w = e < 2 ? c.x : c.y;
+    return (int)((w >> (16 * (e & 1))) & 0xffffu);
+  }
+};
+constexpr int EX_CH = 4;  // entries per exact-list chunk
 
 // Chunks of a list fetched ahead of use: the chunk loads come from HBM (the
 // lists of all workgroups do not fit in L2), so several are kept in flight.
@@ -375,30 +393,33 @@ __device__ __forceinline__ int chunk_entry(const uint4& c, int e) {
 #endif
 constexpr int LIST_PREFETCH = PAMD_LIST_PREFETCH;
 
-// Visits chunks first, first + STEP, ... of row `row` of a chunked list
-// (chunk c at list[(c * rows + row) * 8]) with LIST_PREFETCH chunk loads in
-// flight, calling after_chunk() after each chunk.  The row's last chunk is
-// padded with slot indices; entries past cnt are passed with valid = false.
-template <int STEP, typename Pair, typename Chunk>
+// Visits chunks first, first + STEP, ... of row `row` of a list in chunks of
+// CH entries (chunk c at list[(c * rows + row) * CH]) with LIST_PREFETCH
+// chunk loads in flight, calling after_chunk() after each chunk.  The row's
+// last chunk is padded with slot indices; entries past cnt are passed with
+// valid = false.
+template <int CH, int STEP, typename Pair, typename After>
 __device__ __forceinline__ void for_each_listed(const uint16_t* list, int rows, int row, int cnt,
-                                                int first, Pair&& pair, Chunk&& after_chunk) {
-  const uint4* nb = reinterpret_cast<const uint4*>(list) + row;
-  const int nch = (cnt + 7) >> 3;
-  uint4 q[LIST_PREFETCH];
+                                                int first, Pair&& pair, After&& after_chunk) {
+  typedef ChunkOf<CH> C;
+  typedef typename C::T T;
+  const T* nb = reinterpret_cast<const T*>(list) + row;
+  const int nch = (cnt + CH - 1) / CH;
+  T q[LIST_PREFETCH];
 #pragma unroll
   for (int i = 0; i < LIST_PREFETCH; ++i) {
     const int c = first + i * STEP;
-    q[i] = c < nch ? nb[(size_t)c * rows] : make_uint4(0u, 0u, 0u, 0u);
+    q[i] = c < nch ? nb[(size_t)c * rows] : C::zero();
   }
   for (int ch = first; ch < nch; ch += STEP) {
-    const uint4 cur = q[0];
+    const T cur = q[0];
 #pragma unroll
     for (int i = 0; i + 1 < LIST_PREFETCH; ++i) q[i] = q[i + 1];
     const int ahead = ch + LIST_PREFETCH * STEP;
     q[LIST_PREFETCH - 1] = ahead < nch ? nb[(size_t)ahead * rows] : cur;
-    const int k0 = ch * 8;
+    const int left = cnt - ch * CH;  // valid entries from this chunk on
 #pragma unroll
-    for (int e = 0; e < 8; ++e) pair(chunk_entry(cur, e), k0 + e < cnt);
+    for (int e = 0; e < CH; ++e) pair(C::entry(cur, e), e < left);
     after_chunk();
   }
 }
@@ -433,7 +454,7 @@ __device__ __forceinline__ void pass1_part(const PathArgs& a, const TileLDS& L,
   // lands on the next free position and is overwritten); whole chunks of 8
   // are stored to the exact list with one 16-byte store
   lds_u16* ring = L.stage + STAGE * threadIdx.x;
-  uint4* exr = reinterpret_cast<uint4*>(ts.ex) + er;
+  uint2* exr = reinterpret_cast<uint2*>(ts.ex) + er;
   uint32_t acc = 0, done = 0;  // entries accepted / stored
   auto body = [&](int t, bool valid, auto record) {
     const double dx = wrap_u(xs - L.X[XS * t + 0]);
@@ -485,22 +506,26 @@ __device__ __forceinline__ void pass1_part(const PathArgs& a, const TileLDS& L,
       }
     }
   };
-  // Stores the ring's oldest chunk when it is complete (at most 15 entries
-  // are pending); otherwise the same store goes to the row's last (spare)
-  // chunk, never read, which keeps the loop free of branches.
-  const uint32_t spare = (uint32_t)(a.kmax + EX_PAD) / (8u * STEP) - 1u;  // erows = STEP * N
+  // Stores the ring's oldest 4-entry chunk when it is complete (at most 11
+  // entries are pending after a list chunk); otherwise the same store goes
+  // to the row's last (spare) chunk, never read, which keeps the loop free
+  // of branches.
+  const uint32_t spare = (uint32_t)(a.kmax + EX_PAD) / (EX_CH * STEP) - 1u;  // erows = STEP N
   auto flush = [&](bool full) {
-    const uint32_t c = full ? (done >> 3) : spare;
-    exr[(size_t)c * erows] = *(const uint4*)(ring + (done & (STAGE - 1)));
-    done += full ? 8u : 0u;
+    const uint32_t c = full ? (done >> 2) : spare;
+    exr[(size_t)c * erows] = *(const uint2*)(ring + (done & (STAGE - 1)));
+    done += full ? 4u : 0u;
   };
   const int cnt = ts.cnt[s];
   if (cnt >= 0) {
-    for_each_listed<STEP>(
+    for_each_listed<8, STEP>(
         ts.nbr, N, s, cnt, part, [&](int t, bool valid) { body(t, valid, std::true_type{}); },
-        [&]() { flush(acc - done >= 8u); });
+        [&]() {
+          flush(acc - done >= 4u);
+          flush(acc - done >= 4u);
+        });
     if (acc > done) {  // pad the last chunk with the slot itself
-      for (uint32_t k = acc; k & 7u; ++k) ring[k & (STAGE - 1)] = (uint16_t)s;
+      for (uint32_t k = acc; k & 3u; ++k) ring[k & (STAGE - 1)] = (uint16_t)s;
       flush(true);
     }
     L.ecnt[er] = (int)acc;
@@ -591,7 +616,7 @@ __device__ __forceinline__ void pass2_part(const PathArgs& a, const TileLDS& L, 
   };
   const int ec = L.ecnt[er];
   if (ec >= 0)
-    for_each_listed<1>(
+    for_each_listed<EX_CH, 1>(
         ts.ex, erows, er, ec, 0, [&](int t, bool valid) { body(t, valid, std::false_type{}); },
         [] {});
   else
