@@ -54,7 +54,7 @@ int fail(int code, const char* fmt, ...) {
 constexpr size_t kLdsMax = 163840;  // LDS per workgroup on gfx950
 constexpr int kMaxGrid = 2048;      // persistent-grid cap: bounds per-block scratch
 constexpr size_t kAlign = 256;
-constexpr double kDefaultSkin = 0.45;  // in units of sigma
+constexpr double kDefaultSkin = 0.5;  // in units of sigma
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
@@ -136,32 +136,6 @@ bool cached_tuning(const pamd_path* p, const pamd_potential* v, pamd_tuning* out
 // ---------------------------------------------------------------------------
 // Planning
 // ---------------------------------------------------------------------------
-struct CellGrid {
-  int nc = 0, reach = 0;
-};
-
-// Cells of edge >= radius / reach, stencil of (2 reach + 1)^3 distinct cells;
-// the variant visiting fewer candidate atoms wins; nc = 0 means all pairs.
-CellGrid choose_cells(double box, double radius, int n_atoms) {
-  CellGrid g;
-  const double rho = n_atoms / (box * box * box);
-  double best = (double)n_atoms;  // all pairs
-  const int cap = std::max(64, 4 * n_atoms);
-  for (int reach = 1; reach <= 3; ++reach) {
-    int nc = (int)std::floor(reach * box / radius);
-    while (nc >= 2 * reach + 1 && (int64_t)nc * nc * nc > cap) --nc;
-    if (nc < 2 * reach + 1) continue;
-    const double h = box / nc;
-    const double cand = std::pow(2 * reach + 1, 3) * h * h * h * rho;
-    if (cand < best) {
-      best = cand;
-      g.nc = nc;
-      g.reach = reach;
-    }
-  }
-  return g;
-}
-
 int default_kmax(double box, double radius, int n_atoms) {
   const double rho = n_atoms / (box * box * box);
   const double expect = 4.0 / 3.0 * M_PI * radius * radius * radius * rho;
@@ -238,7 +212,6 @@ int make_plan(const pamd_path* p, const pamd_potential* v, const pamd_tuning* t_
     const double L = v->box;
     P.skin = t.skin > 0 ? t.skin : (have_cache && cached.skin > 0 ? cached.skin : kDefaultSkin * v->sigma);
     const double radius = v->rc + P.skin;
-    P.cells = choose_cells(L, radius, N);
     P.kmax = t.max_neighbours > 0 ? std::min(t.max_neighbours, std::max(1, N - 1))
                                   : default_kmax(L, radius, N);
     P.kmax = (int)align_up((size_t)P.kmax, 8);  // lists are read in chunks of 8
@@ -252,21 +225,17 @@ int make_plan(const pamd_path* p, const pamd_potential* v, const pamd_tuning* t_
     P.tile = (int)std::min<int64_t>(tile, P.steps);
     P.n_tiles = (int)((P.steps + P.tile - 1) / P.tile);
     P.grid = std::min(P.n_tiles, kMaxGrid);
-    const bool half_ok = N <= fused_half_slots() * P.block &&
-                         fused_lds_bytes(N, P.cells.nc, false, true, P.block) <= kLdsMax;
-    if (list == PAMD_LIST_HALF && !half_ok)
-      return fail(PAMD_EUNSUPPORTED, "half lists need n_atoms <= %d * block and LDS for 2 slice arrays", fused_half_slots());
     P.half = list == PAMD_LIST_HALF;  // automatic choice: full lists (repeatable, as fast)
-    const size_t lds_r = fused_lds_bytes(N, P.cells.nc, true, P.half, P.block);
-    const size_t lds_g = fused_lds_bytes(N, P.cells.nc, false, P.half, P.block);
-    if (lds_r <= kLdsMax) {
+    if (P.half && N > fused_half_slots() * P.block)
+      return fail(PAMD_EUNSUPPORTED, "half lists need n_atoms <= %d * block", fused_half_slots());
+    // residuals in LDS (two slot arrays) when they fit, else in global scratch
+    if (fused_cells_fit(L, radius, N, P.block, true, P.half, &P.cells, &P.lds)) {
       P.r_in_lds = true;
-      P.lds = lds_r;
-    } else if (lds_g <= kLdsMax) {
+    } else if (fused_cells_fit(L, radius, N, P.block, false, P.half, &P.cells, &P.lds)) {
       P.r_in_lds = false;
-      P.lds = lds_g;
     } else {
-      return fail(PAMD_EUNSUPPORTED, "n_atoms = %d needs %zu bytes of LDS per workgroup (max %zu)", N, lds_g, kLdsMax);
+      return fail(PAMD_EUNSUPPORTED, "n_atoms = %d needs %zu bytes of LDS per workgroup (max %zu)", N,
+                  fused_lds_bytes(N, 0, false, P.half, P.block), kLdsMax);
     }
     P.off_bnd = bump(cur, sizeof(double) * 3 * N * (size_t)std::max(0, P.n_tiles - 1));
     // neighbour list, then the exact list; both with one spare chunk per atom
@@ -274,7 +243,7 @@ int make_plan(const pamd_path* p, const pamd_potential* v, const pamd_tuning* t_
     // per atom, each with a spare chunk: kmax + 32 per atom); both get the
     // larger size
     P.nbr_stride = 2 * align_up((size_t)(P.kmax + 32) * N, 128);
-    P.cnt_stride = align_up((size_t)N, 64);
+    P.cnt_stride = align_up((size_t)2 * N, 64);  // list lengths: up to two rows per atom
     P.xref_stride = align_up((size_t)6 * N, 32);
     P.rglob_stride = P.r_in_lds ? 0 : align_up((size_t)3 * N, 32);
     P.off_nbr = bump(cur, sizeof(uint16_t) * P.nbr_stride * P.grid);
@@ -283,7 +252,7 @@ int make_plan(const pamd_path* p, const pamd_potential* v, const pamd_tuning* t_
     P.off_rglob = bump(cur, sizeof(double) * P.rglob_stride * P.grid);
   } else {
     const int N = P.N;
-    P.pcells = choose_cells(v->box, v->rc, N);
+    P.pcells = choose_cells(v->box, v->rc, N, 1 << 30);
     P.pkmax = t.max_neighbours > 0 ? std::min(t.max_neighbours, std::max(1, N - 1))
                                    : default_kmax(v->box, v->rc, N);
     P.block = t.block ? t.block : 256;
@@ -432,6 +401,43 @@ int evaluate(const pamd_path* p, const pamd_potential* v, const Plan& P, const d
 }  // namespace
 
 namespace pamd {
+
+CellGrid choose_cells(double box, double radius, int n_atoms, int max_cells) {
+  CellGrid g;
+  const double rho = n_atoms / (box * box * box);
+  double best = (double)n_atoms;  // all pairs
+  const int cap = std::min(max_cells, std::max(64, 4 * n_atoms));
+  for (int reach = 1; reach <= 3; ++reach) {
+    int nc = (int)std::floor(reach * box / radius);
+    while (nc >= 2 * reach + 1 && (int64_t)nc * nc * nc > cap) --nc;
+    if (nc < 2 * reach + 1) continue;
+    const double h = box / nc;
+    const double cand = std::pow(2 * reach + 1, 3) * h * h * h * rho;
+    if (cand < best) {
+      best = cand;
+      g.nc = nc;
+      g.reach = reach;
+    }
+  }
+  return g;
+}
+
+bool fused_cells_fit(double box, double radius, int n_atoms, int block, bool r_in_lds, bool half,
+                     CellGrid* grid, size_t* lds) {
+  int cap = 1 << 30;
+  for (;;) {
+    const CellGrid g = choose_cells(box, radius, n_atoms, cap);
+    const size_t b = fused_lds_bytes(n_atoms, g.nc, r_in_lds, half, block);
+    if (b <= kFusedLdsMax) {
+      *grid = g;
+      *lds = b;
+      return true;
+    }
+    if (g.nc == 0) return false;
+    cap = g.nc * g.nc * g.nc / 2;  // fewer, larger cells
+  }
+}
+
 int batch_fail(int code, const char* fmt, ...) {
   char buf[512];
   va_list ap;

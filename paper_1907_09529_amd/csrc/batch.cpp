@@ -26,7 +26,6 @@ int batch_fail(int code, const char* fmt, ...);
 namespace {
 
 constexpr size_t kAlign = 256;
-constexpr size_t kLdsMax = 163840;
 constexpr int kMaxGrid = 2048;
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
@@ -34,30 +33,6 @@ size_t bump(size_t& cur, size_t bytes) {
   const size_t at = align_up(cur, kAlign);
   cur = at + bytes;
   return at;
-}
-
-struct CellChoice {
-  int nc = 0, reach = 0;
-};
-
-CellChoice cells_for(double box, double radius, int n_atoms) {
-  CellChoice g;
-  const double rho = n_atoms / (box * box * box);
-  double best = (double)n_atoms;
-  const int cap = std::max(64, 4 * n_atoms);
-  for (int reach = 1; reach <= 3; ++reach) {
-    int nc = (int)std::floor(reach * box / radius);
-    while (nc >= 2 * reach + 1 && (int64_t)nc * nc * nc > cap) --nc;
-    if (nc < 2 * reach + 1) continue;
-    const double h = box / nc;
-    const double cand = std::pow(2 * reach + 1, 3) * h * h * h * rho;
-    if (cand < best) {
-      best = cand;
-      g.nc = nc;
-      g.reach = reach;
-    }
-  }
-  return g;
 }
 
 }  // namespace
@@ -119,16 +94,17 @@ int pamd_batch_create(int32_t n_paths, const pamd_path* paths, const pamd_potent
 
   // Lennard-Jones members: per-member tiles and lists, batch-wide launch shape.
   int max_n = 1;
-  size_t max_lds_r = 0, max_lds_g = 0, max_lds_rh = 0, max_lds_gh = 0, max_nbr = 0;
+  size_t max_nbr = 0;
+  std::vector<double> radii;  // list radius per member (LJ members, in order)
   int64_t bnd_elems = 0;
   const double skin_in = tuning && tuning->skin > 0 ? tuning->skin : -1.0;
   for (int p : b->lj_ids) {
     const pamd_path& P = paths[p];
     const pamd_potential& V = pots[p];
     const int N = P.n_atoms;
-    const double skin = skin_in > 0 ? skin_in : 0.45 * V.sigma;
+    const double skin = skin_in > 0 ? skin_in : 0.5 * V.sigma;
     const double radius = V.rc + skin;
-    CellChoice cc = cells_for(V.box, radius, N);
+    radii.push_back(radius);
     const double rho = N / (V.box * V.box * V.box);
     int kmax = (int)align_up((size_t)std::ceil(1.3 * 4.0 / 3.0 * M_PI * radius * radius * radius * rho + 24.0), 8);
     if (tuning && tuning->max_neighbours > 0) kmax = tuning->max_neighbours;
@@ -157,8 +133,6 @@ int pamd_batch_create(int32_t n_paths, const pamd_path* paths, const pamd_potent
     a.lj.duc = -(24.0 * V.eps / V.rc) * (2.0 * sr6 * sr6 - sr6);
     a.rlist2 = radius * radius;
     a.half_skin2 = 0.25 * skin * skin;
-    a.nc = cc.nc;
-    a.reach = cc.reach;
     a.kmax = kmax;
     set_box_units(a);
     m.x_off = b->x_off[p];
@@ -169,10 +143,6 @@ int pamd_batch_create(int32_t n_paths, const pamd_path* paths, const pamd_potent
     b->slots.push_back(p);
     b->max_tiles = std::max(b->max_tiles, a.n_tiles);
     max_n = std::max(max_n, N);
-    max_lds_r = std::max(max_lds_r, fused_lds_bytes(N, cc.nc, true, false, 0));
-    max_lds_g = std::max(max_lds_g, fused_lds_bytes(N, cc.nc, false, false, 0));
-    max_lds_rh = std::max(max_lds_rh, fused_lds_bytes(N, cc.nc, true, true, 0));
-    max_lds_gh = std::max(max_lds_gh, fused_lds_bytes(N, cc.nc, false, true, 0));
     max_nbr = std::max(max_nbr, (size_t)(kmax + 32) * N);  // exact lists: 2 rows, spare chunks
   }
   // Work list: every tile of every member, largest (atoms x steps) first.
@@ -204,32 +174,38 @@ int pamd_batch_create(int32_t n_paths, const pamd_path* paths, const pamd_potent
       block = (int)align_up((size_t)2 * max_n, 64);
     }
     L.block = std::max(64, std::min(1024, block));
-    const size_t stage = fused_lds_stage_bytes(L.block);
-    max_lds_r += stage;
-    max_lds_g += stage;
-    max_lds_rh += stage;
-    max_lds_gh += stage;
-    const bool half_ok = max_n <= fused_half_slots() * L.block && max_lds_gh <= kLdsMax;
-    if (list == PAMD_LIST_HALF && !half_ok) {
+    L.half = list == PAMD_LIST_HALF;  // automatic choice: full lists
+    if (L.half && max_n > fused_half_slots() * L.block) {
       delete b;
       return batch_fail(PAMD_EUNSUPPORTED, "half lists do not fit this batch");
     }
-    L.half = list == PAMD_LIST_HALF;  // automatic choice: full lists
-    const size_t lr = L.half ? max_lds_rh : max_lds_r, lg = L.half ? max_lds_gh : max_lds_g;
-    if (lr <= kLdsMax) {
-      L.r_in_lds = true;
-      L.lds_bytes = lr;
-    } else if (lg <= kLdsMax) {
-      L.r_in_lds = false;
-      L.lds_bytes = lg;
-    } else {
+    // one residual placement for the whole batch: in LDS if every member
+    // fits so, else in global scratch; each member gets the finest cell grid
+    // that fits
+    auto fit_all = [&](bool r_in_lds) {
+      size_t lds_max = 0;
+      for (size_t mi = 0; mi < b->members.size(); ++mi) {
+        PathArgs& a = b->members[mi].a;
+        CellGrid g;
+        size_t lds = 0;
+        if (!fused_cells_fit(a.lj.box, radii[mi], a.n_atoms, L.block, r_in_lds, L.half, &g, &lds))
+          return false;
+        a.nc = g.nc;
+        a.reach = g.reach;
+        lds_max = std::max(lds_max, lds);
+      }
+      L.r_in_lds = r_in_lds;
+      L.lds_bytes = lds_max;
+      return true;
+    };
+    if (!fit_all(true) && !fit_all(false)) {
       delete b;
       return batch_fail(PAMD_EUNSUPPORTED, "batch member with %d atoms exceeds LDS", max_n);
     }
     L.grid = std::max(1, std::min<int>((int)b->items.size(), kMaxGrid));
   }
   b->nbr_stride = 2 * align_up(max_nbr, 128);  // neighbour list + exact list
-  b->cnt_stride = align_up((size_t)max_n, 64);
+  b->cnt_stride = align_up((size_t)2 * max_n, 64);  // list lengths: up to two rows per atom
   b->xref_stride = align_up((size_t)6 * max_n, 32);
   b->rglob_stride = L.r_in_lds ? 0 : align_up((size_t)3 * max_n, 32);
   size_t cur = 0;

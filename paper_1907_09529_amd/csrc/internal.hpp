@@ -27,9 +27,14 @@ struct LJConst {
 //   Hessian    K w = -fs w + [(a96_L2 p (7 sr6 - 2) + duc_L iru) ir2] (du.w) du,
 // with iru = 1/|du|, ir2 = iru^2, sr6 = (sig2 ir2)^3, p = ir2 sr6 and
 // fs = a24_L2 p (2 sr6 - 1) + duc_L iru (the physical -U'(r)/r).
+// With ir6 = ir2^3 and ir8 = ir2 ir6 the same terms are polynomials in ir6:
+//   force coefficient  ir8 (f12 ir6 - f6) + duc iru,
+//   fs                 ir8 (s12 ir6 - s6) + duc_L iru,
+//   bv                 [ir8 (b12 ir6 - b6) + duc_L iru] ir2.
 struct BoxUnits {
   double rc2, sig2, rlist2, half_skin2;
   double a24_L, a24_L2, a96_L2, duc, duc_L, seven;
+  double f12, f6, s12, s6, b12, b6;
 };
 
 // One path as seen by the LJ kernels.
@@ -74,6 +79,13 @@ inline void set_box_units(PathArgs& a) {
   a.bu.duc = a.lj.duc;
   a.bu.duc_L = a.lj.duc * ib;
   a.bu.seven = 7.0;
+  const double sg6 = a.bu.sig2 * a.bu.sig2 * a.bu.sig2, sg12 = sg6 * sg6;
+  a.bu.f12 = 2.0 * a.bu.a24_L * sg12;
+  a.bu.f6 = a.bu.a24_L * sg6;
+  a.bu.s12 = 2.0 * a.bu.a24_L2 * sg12;
+  a.bu.s6 = a.bu.a24_L2 * sg6;
+  a.bu.b12 = 7.0 * a.bu.a96_L2 * sg12;
+  a.bu.b6 = 2.0 * a.bu.a96_L2 * sg6;
 }
 
 // Per-block scratch in global memory for the fused LJ kernel.
@@ -120,11 +132,24 @@ struct BatchBase {
   int32_t pad0;
 };
 
-// Shared memory of the fused kernel's workgroup: the part that grows with
-// the block size is fused_lds_stage_bytes(block), included in the total.
+// Shared memory of the fused kernel's workgroup (bytes).
 size_t fused_lds_bytes(int n_atoms, int nc, bool r_in_lds, bool half, int block);
-size_t fused_lds_stage_bytes(int block);
 int fused_half_slots();
+constexpr size_t kFusedLdsMax = 163840;  // LDS per workgroup on gfx950
+
+// Cell grid of a list build: nc cells per axis (0: all pairs), stencil
+// half-width `reach` cells.
+struct CellGrid {
+  int nc = 0, reach = 0;
+};
+// Cells of edge >= radius / reach for reach in 1..3, at most max_cells of
+// them (and at most 4 per atom); the variant visiting the fewest candidate
+// atoms wins.
+CellGrid choose_cells(double box, double radius, int n_atoms, int max_cells);
+// The finest cell grid with which the fused kernel's LDS (given block size,
+// residual placement and list kind) fits kFusedLdsMax; false if none does.
+bool fused_cells_fit(double box, double radius, int n_atoms, int block, bool r_in_lds, bool half,
+                     CellGrid* grid, size_t* lds);
 size_t plain_lds_bytes(int n_atoms, int nc);
 
 hipError_t launch_lj_fused(const PathArgs& a, const BlockScratch& s, const FusedLaunch& L,

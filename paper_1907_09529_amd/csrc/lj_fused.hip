@@ -43,29 +43,47 @@ namespace pamd {
 typedef __attribute__((address_space(3))) double lds_f64;
 typedef __attribute__((address_space(3))) int lds_i32;
 typedef __attribute__((address_space(3))) uint16_t lds_u16;
+typedef __attribute__((address_space(3))) int16_t lds_i16;
 
 constexpr int HALF_SLOTS = 2;  // atoms per thread supported by the half-list kernel
 constexpr int EX_PAD = 32;     // exact-list entries per atom beyond kmax (see TileScratch)
 
-// Shared-memory layout of one tile.  With rho in LDS every slot holds 6
-// doubles, its position u (0..2) and rho (3..5), so that pass 2 reads both
-// from one address; otherwise 3 (positions only; rho lives in global scratch).
+// Shared-memory layout of one tile.  With rho in LDS every slot holds
+// XS_R = 7 doubles, its position u (0..2), rho (3..5) and one unused, so that
+// pass 2 reads both from one address, and there are two slot arrays: slice
+// n + 1 is loaded into one while pass 2 of slice n reads the other.  The
+// 56-byte stride (14 four-byte banks) spreads the slots of either parity over
+// as many LDS banks as a 48-byte stride spreads all slots; each lane reads
+// partners of one slot parity (see rebuild).  Otherwise a slot holds 3
+// doubles (positions only; rho lives in global scratch) and there is one
+// array.
+constexpr int XS_R = 7;
 struct TileLDS {
-  lds_f64* X;     // stride XS: slice x_n / L, sorted slots
+  lds_f64* X;     // stride XS: slice x_n / L, sorted slots (the array in use)
+  lds_f64* X2;    // the other slot array (== X when there is one)
   lds_f64* ACC;   // 3 * n_atoms, partner-share accumulator (half lists)
   lds_f64* red;   // 32 doubles
-  lds_u16* stage; // 16 per thread: ring of exact-list entries not yet stored
-  lds_i32* perm;  // n_atoms: slot -> original atom index
-  lds_i32* perm2; // n_atoms: scratch for re-sorting
-  lds_i32* ecnt;  // 2 n_atoms: exact-list lengths this slice (-1: not recorded)
   lds_i32* tmp;   // 16
-  lds_i32* start; // ncell + 1: first slot of each cell
-  lds_i32* fill;  // ncell
-  lds_i32* atoms; // n_atoms: slots in cell order
+  lds_i32* flag;  // 2: slice m needs a list rebuild (flag[m & 1] != 0)
+  lds_u16* perm;  // n_atoms: slot -> original atom index
+  lds_i16* ecnt;  // 2 n_atoms: exact-list lengths this slice (-1: not recorded)
+  // Pass 1 and the list build never run at the same time, so their scratch
+  // shares one region:
+  lds_u16* stage; // pass 1: 16 per thread, ring of exact-list entries not yet stored
+  lds_i32* start; // build: ncell + 1, first slot of each cell
+  lds_i32* fill;  // build: ncell
+  lds_u16* perm2; // build: n_atoms, scratch for re-sorting
+  lds_u16* atoms; // build: n_atoms, slots in cell order
 };
 
 // Shared-memory bytes of one tile (see carve_lds).
 constexpr uint32_t STAGE = 16;  // exact-list staging entries per thread
+
+__host__ __device__ inline uint32_t lds_shared_region(int n_atoms, int ncell, int block) {
+  const uint32_t ring = 2u * STAGE * (uint32_t)block;
+  const uint32_t build = 4u * (2u * (uint32_t)ncell + 1u) + 4u * (uint32_t)n_atoms;
+  return ring > build ? ring : build;
+}
 
 __device__ inline TileLDS carve_lds(char* base_generic, int n_atoms, int ncell, bool r_in_lds,
                                     bool half) {
@@ -78,33 +96,31 @@ __device__ inline TileLDS carve_lds(char* base_generic, int n_atoms, int ncell, 
     off += 8u * n;
     return p;
   };
-  auto i32 = [&](uint32_t n) {
-    lds_i32* p = (lds_i32*)(base + off);
-    off += 4u * n;
-    return p;
-  };
-  t.X = f64((r_in_lds ? 6u : 3u) * n_atoms);
+  t.X = f64((uint32_t)(r_in_lds ? XS_R : 3) * n_atoms);
+  t.X2 = r_in_lds ? f64((uint32_t)XS_R * n_atoms) : t.X;
   t.ACC = half ? f64(3u * n_atoms) : nullptr;
   t.red = f64(32);
+  t.tmp = (lds_i32*)(base + off);
+  t.flag = t.tmp + 16;
+  off += 4u * 18u;
+  t.perm = (lds_u16*)(base + off);
+  off += 2u * n_atoms;
+  t.ecnt = (lds_i16*)(base + off);
+  off += 4u * n_atoms;
   off = (off + 15u) & ~15u;
   t.stage = (lds_u16*)(base + off);
-  off += 2u * STAGE * blockDim.x;
-  t.perm = i32(n_atoms);
-  t.perm2 = i32(n_atoms);
-  t.ecnt = i32(2u * n_atoms);
-  t.tmp = i32(16);
-  t.start = i32(ncell + 1);
-  t.fill = i32(ncell);
-  t.atoms = i32(n_atoms);
+  t.start = (lds_i32*)(base + off);
+  t.fill = t.start + ncell + 1;
+  t.perm2 = (lds_u16*)(t.fill + ncell);
+  t.atoms = t.perm2 + n_atoms;
   return t;
 }
 
 size_t fused_lds_bytes(int n_atoms, int nc, bool r_in_lds, bool half, int block) {
   const size_t ncell = (size_t)nc * nc * nc;
-  size_t b = sizeof(double) * (size_t)n_atoms * ((r_in_lds ? 6 : 3) + (half ? 3 : 0));
-  b += sizeof(double) * 32 + 16 + 2 * STAGE * (size_t)block + sizeof(int) * 16;
-  b += sizeof(int) * 5 * (size_t)n_atoms;
-  b += sizeof(int) * (2 * ncell + 1);
+  size_t b = sizeof(double) * (size_t)n_atoms * ((r_in_lds ? 2 * XS_R : 3) + (half ? 3 : 0));
+  b += sizeof(double) * 32 + sizeof(int) * 18 + 6 * (size_t)n_atoms + 16;
+  b += lds_shared_region(n_atoms, (int)ncell, block);
   return b;
 }
 
@@ -115,9 +131,10 @@ int fused_half_slots() { return HALF_SLOTS; }
 // Per-block global scratch for one tile: lists and per-atom state that only
 // the owning thread touches.
 struct TileScratch {
-  uint16_t* nbr;   // (kmax + EX_PAD) * n_atoms: chunks of 8 entries, [(k/8) N + s] * 8 + k%8
-  uint16_t* ex;    // same layout: the partners within r_c at the current slice (exact list)
-  int* cnt;        // n_atoms
+  uint16_t* nbr;   // (kmax + EX_PAD) * n_atoms: R rows (R = n_atoms for half lists, 2 n_atoms
+                   // for full ones) in chunks of 8 entries, entry k of row r at [(k/8) R + r] * 8 + k%8
+  uint16_t* ex;    // 2 n_atoms rows in chunks of 4: the partners within r_c at the current slice
+  int* cnt;        // R: entries per row
   double* xref;    // 3 * n_atoms: positions u (sorted slots) at the last list build
   double* rprev;   // 3 * n_atoms: rho_{n-1}, by original atom index
   double* rglob;   // 3 * n_atoms: rho_n (sorted slots) when not in LDS; sort scratch
@@ -163,7 +180,7 @@ __device__ void sort_cells(int N, int nc, const TileLDS& L) {
   for (int c = threadIdx.x; c < ncell; c += B) L.fill[c] = L.start[c];
   __syncthreads();
   for (int s = threadIdx.x; s < N; s += B)
-    L.atoms[atomicAdd((int*)&L.fill[cell_of_slot<XS>(L.X, s, nc)], 1)] = s;
+    L.atoms[atomicAdd((int*)&L.fill[cell_of_slot<XS>(L.X, s, nc)], 1)] = (uint16_t)s;
   __syncthreads();
   for (int c = threadIdx.x; c < ncell; c += B) {
     const int lo = L.start[c], hi = L.start[c + 1];
@@ -174,16 +191,26 @@ __device__ void sort_cells(int N, int nc, const TileLDS& L) {
         L.atoms[b + 1] = L.atoms[b];
         --b;
       }
-      L.atoms[b + 1] = v;
+      L.atoms[b + 1] = (uint16_t)v;
     }
   }
   __syncthreads();
+}
+
+// Entries per list row: one row per atom for half lists; for full lists two
+// rows per atom (parts 0 and 1: partners of even and odd slot index), each
+// with room for half of kmax plus a spare chunk.
+template <bool HALF>
+__device__ __forceinline__ int row_capacity(int kmax) {
+  return HALF ? kmax : ((kmax / 2 + 15) & ~7);
 }
 
 // (Re)builds the neighbour lists of the slice in L.X.  With cells, atoms are
 // first re-sorted into cell order (slots and perm are rewritten).
 template <int XS, bool HALF>
 __device__ void rebuild(const PathArgs& a, const TileLDS& L, const TileScratch& ts) {
+  constexpr int PARTS = HALF ? 1 : 2;
+  constexpr int SPAN = WAVE / PARTS;  // slots per wave
   const int N = a.n_atoms;
   const int B = blockDim.x;
   if (a.nc > 0) {
@@ -195,7 +222,7 @@ __device__ void rebuild(const PathArgs& a, const TileLDS& L, const TileScratch& 
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         const double v = L.X[XS * old + c];
-        if constexpr (XS == 6)
+        if constexpr (XS == XS_R)
           L.X[XS * s + 3 + c] = v;
         else
           ts.rglob[3 * s + c] = v;
@@ -206,7 +233,7 @@ __device__ void rebuild(const PathArgs& a, const TileLDS& L, const TileScratch& 
     for (int s = threadIdx.x; s < N; s += B) {
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        if constexpr (XS == 6)
+        if constexpr (XS == XS_R)
           L.X[XS * s + c] = L.X[XS * s + 3 + c];
         else
           L.X[XS * s + c] = ts.rglob[3 * s + c];
@@ -218,23 +245,28 @@ __device__ void rebuild(const PathArgs& a, const TileLDS& L, const TileScratch& 
   const int nc = a.nc, reach = a.reach;
   const double rl2 = a.bu.rlist2;
   const int lane = threadIdx.x & (WAVE - 1);
-  // entry k of slot s lives at nbr[((k >> 3) * N + s) * 8 + (k & 7)]; woff
+  const int part = PARTS == 1 ? 0 : lane / SPAN;
+  const int R = PARTS * N;  // list rows
+  // entry k of row r lives at nbr[((k >> 3) * R + r) * 8 + (k & 7)]; woff
   // tracks that offset as entries are appended (woff & 7 == k & 7)
-  const uint32_t step8 = 8u * N - 7u;
-  const uint32_t cap = (uint32_t)a.kmax * (uint32_t)N;  // offset span of kmax entries
-  // Each wave scans, for its 64 consecutive slots, the union of their cell
-  // stencils: the candidate index is wave-uniform (LDS broadcast reads, no
-  // divergent loop bounds); every lane tests the candidate against its atom.
-  for (int base = threadIdx.x - lane; base < N; base += B) {
-    const int s = base + lane;
+  const uint32_t step8 = 8u * R - 7u;
+  const uint32_t cap = (uint32_t)row_capacity<HALF>(a.kmax) * (uint32_t)R;  // offset span of a row
+  const int wv = threadIdx.x / WAVE, nwv = B / WAVE;
+  // Each wave takes SPAN consecutive slots and scans the union of their cell
+  // stencils: the candidate pair index is wave-uniform (LDS broadcast reads,
+  // no divergent loop bounds); part p of a slot tests the candidates of slot
+  // parity p against its atom, so the two rows of an atom split its partners
+  // evenly and the wave's scan is half as long as one lane per atom would
+  // make it.
+  for (int base = wv * SPAN; base < N; base += nwv * SPAN) {
+    const int s = base + (lane % SPAN);
     const bool live = s < N;
     const int sc = live ? s : base;
     const double xs = L.X[XS * sc], ys = L.X[XS * sc + 1], zs = L.X[XS * sc + 2];
     uint16_t* nb = ts.nbr;
-    const uint32_t wbase = 8u * (uint32_t)sc;
+    const uint32_t wbase = 8u * (uint32_t)(PARTS * sc + part);
     const uint32_t wcap = wbase + cap;
-    // a lane past the last slot never accepts; its stores go to the spare
-    // chunk of slot sc, which is never read
+    // a lane past the last slot never appends
     uint32_t woff = live ? wbase : wcap;
     bool over = false;
     auto append = [&](int t) {
@@ -243,33 +275,36 @@ __device__ void rebuild(const PathArgs& a, const TileLDS& L, const TileScratch& 
       over |= !room;
       woff += room ? ((woff & 7u) == 7u ? step8 : 1u) : 0u;
     };
-    // Candidates [t0, t1) are wave-uniform (LDS broadcast reads).  They are
-    // tested in groups of up to 32: each lane collects its accepted
-    // candidates in a bit mask, then appends them in a short loop over the
-    // set bits, so the test loop itself has no stores and no branches.
+    // Candidates [t0, t1) are wave-uniform.  Each lane tests those of its
+    // parity in groups of up to 32, collecting the accepted ones in a bit
+    // mask, then appends them in a short loop over the set bits, so the test
+    // loop itself has no stores and no branches.
     auto scan = [&](int t0, int t1) {
       t0 = __builtin_amdgcn_readfirstlane(t0);
       t1 = __builtin_amdgcn_readfirstlane(t1);
-      for (int g = t0; g < t1; g += 32) {
-        const int gn = min(32, t1 - g);
+      // candidate of lane-part p at position j of a group starting at g:
+      // g + PARTS * j + q, with q chosen so that its slot parity is p
+      const int q = PARTS == 1 ? 0 : ((part - t0) & 1);
+      for (int g = t0; g < t1; g += 32 * PARTS) {
         uint32_t bits = 0;
-        for (int j = 0; j < gn; j += 4) {
+        for (int j = 0; j < 32; j += 4) {
+          if (g + PARTS * j >= t1) break;
           double px[4], py[4], pz[4];
 #pragma unroll
           for (int u = 0; u < 4; ++u) {
-            const int t = min(g + j + u, t1 - 1);
+            const int t = min(g + PARTS * (j + u) + q, t1 - 1);
             px[u] = L.X[XS * t + 0];
             py[u] = L.X[XS * t + 1];
             pz[u] = L.X[XS * t + 2];
           }
 #pragma unroll
           for (int u = 0; u < 4; ++u) {
-            const int t = g + j + u;
+            const int t = g + PARTS * (j + u) + q;
             const double dx = wrap_u(xs - px[u]);
             const double dy = wrap_u(ys - py[u]);
             const double dz = wrap_u(zs - pz[u]);
             const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
-            const bool pass = j + u < gn && t != s && r2 <= rl2 &&
+            const bool pass = t < t1 && t != s && r2 <= rl2 &&
                               (!HALF || upper_half(dx, dy, dz, s, t));
             bits |= pass ? (1u << (j + u)) : 0u;
           }
@@ -278,7 +313,7 @@ __device__ void rebuild(const PathArgs& a, const TileLDS& L, const TileScratch& 
         while (bits) {
           const int j = __builtin_ctz(bits);
           bits &= bits - 1u;
-          append(g + j);
+          append(g + PARTS * j + q);
         }
       }
     };
@@ -348,10 +383,12 @@ __device__ void rebuild(const PathArgs& a, const TileLDS& L, const TileScratch& 
       // pad the last chunk with the slot itself (read as invalid)
       for (uint32_t o = woff; (o & 7u) != 0u; ++o) nb[o] = (uint16_t)s;
       const uint32_t rel = woff - wbase;
-      const int cnt = (int)((rel & ~7u) / (uint32_t)N + (rel & 7u));
-      ts.cnt[s] = over ? -1 : cnt;
+      const int cnt = (int)((rel & ~7u) / (uint32_t)R + (rel & 7u));
+      ts.cnt[PARTS * s + part] = over ? -1 : cnt;
+      if (part == 0) {
 #pragma unroll
-      for (int c = 0; c < 3; ++c) ts.xref[3 * s + c] = L.X[XS * s + c];
+        for (int c = 0; c < 3; ++c) ts.xref[3 * s + c] = L.X[XS * s + c];
+      }
     }
   }
 }
@@ -436,8 +473,8 @@ __device__ __forceinline__ void for_each_atom(const PathArgs& a, const TileScrat
   }
 }
 
-// Pass 1 for slot s, part `part` of STEP: the force on s from neighbour-list
-// chunks part, part + STEP, ... (the caller adds the STEP partial forces).
+// Pass 1 for slot s, part `part` of STEP: the force on s from list row
+// STEP s + part (the caller adds the STEP partial forces).
 // The partners found within r_c are recorded, in list order, as exact-list
 // row `er` of `erows` (ts.ex, padded with the slot itself to a whole chunk;
 // length in L.ecnt[er]) for pass 2; after an overflow scan no exact list is
@@ -486,9 +523,8 @@ __device__ __forceinline__ void pass1_part(const PathArgs& a, const TileLDS& L,
       double iru = rsqrt_nr(r2);
       iru = ok ? iru : 0.0;
       const double ir2 = iru * iru;
-      const double sr2 = k.sig2 * ir2;
-      const double sr6 = sr2 * sr2 * sr2;
-      const double fsl = fma(k.a24_L * (ir2 * sr6), fma(2.0, sr6, -1.0), k.duc * iru);
+      const double ir6 = ir2 * ir2 * ir2;
+      const double fsl = fma(ir2 * ir6, fma(k.f12, ir6, -k.f6), k.duc * iru);
       fx = fma(fsl, dx, fx);
       fy = fma(fsl, dy, fy);
       fz = fma(fsl, dz, fz);
@@ -516,10 +552,11 @@ __device__ __forceinline__ void pass1_part(const PathArgs& a, const TileLDS& L,
     exr[(size_t)c * erows] = *(const uint2*)(ring + (done & (STAGE - 1)));
     done += full ? 4u : 0u;
   };
-  const int cnt = ts.cnt[s];
+  const int cnt = ts.cnt[STEP * s + part];
   if (cnt >= 0) {
-    for_each_listed<8, STEP>(
-        ts.nbr, N, s, cnt, part, [&](int t, bool valid) { body(t, valid, std::true_type{}); },
+    for_each_listed<8, 1>(
+        ts.nbr, STEP * N, STEP * s + part, cnt, 0,
+        [&](int t, bool valid) { body(t, valid, std::true_type{}); },
         [&]() {
           flush(acc - done >= 4u);
           flush(acc - done >= 4u);
@@ -528,7 +565,7 @@ __device__ __forceinline__ void pass1_part(const PathArgs& a, const TileLDS& L,
       for (uint32_t k = acc; k & 3u; ++k) ring[k & (STAGE - 1)] = (uint16_t)s;
       flush(true);
     }
-    L.ecnt[er] = (int)acc;
+    L.ecnt[er] = (int16_t)acc;
   } else {
     for_each_atom<HALF, STEP>(a, ts, s, part,
                               [&](int t, bool valid) { body(t, valid, std::false_type{}); });
@@ -584,16 +621,21 @@ __device__ __forceinline__ void pass2_part(const PathArgs& a, const TileLDS& L, 
         }
       }
     } else {
-      double iru = rsqrt_nr(r2);
-      iru = ok ? iru : 0.0;
+      // Exact-list entries need no mask: the padding entries name the slot
+      // itself (d = w = 0), and clamping r^2 away from 0 keeps every term
+      // finite, so they add exactly 0.
+      double iru;
+      if constexpr (decltype(check)::value)
+        iru = ok ? rsqrt_nr(r2) : 0.0;
+      else
+        iru = rsqrt_nr(fmax(r2, 1e-30));
       const double ir2 = iru * iru;
-      const double sr2 = k.sig2 * ir2;
-      const double sr6 = sr2 * sr2 * sr2;
-      const double p = ir2 * sr6;
+      const double ir6 = ir2 * ir2 * ir2;
+      const double ir8 = ir2 * ir6;
       const double ducir = k.duc_L * iru;
       // fs = -U'(r)/r;  bv = (U'' - U'/r) L^2 / r^2
-      const double fs = fma(k.a24_L2 * p, fma(2.0, sr6, -1.0), ducir);
-      const double bv = fma(k.a96_L2 * p, fma(sr6, k.seven, -2.0), ducir) * ir2;
+      const double fs = fma(ir8, fma(k.s12, ir6, -k.s6), ducir);
+      const double bv = fma(ir8, fma(k.b12, ir6, -k.b6), ducir) * ir2;
       const double tt = bv * fma(dx, wx, fma(dy, wy, dz * wz));
       if constexpr (HALF) {
         const double kx = fma(-fs, wx, tt * dx);
@@ -625,15 +667,18 @@ __device__ __forceinline__ void pass2_part(const PathArgs& a, const TileLDS& L, 
 }
 
 template <bool F32, bool RLDS, bool HALF>
-__device__ void tile_body(const PathArgs& a, int tile, const TileScratch& ts, char* lds_base) {
-  constexpr int XS = RLDS ? 6 : 3;  // LDS doubles per slot
+__device__ __forceinline__ void tile_body(const PathArgs& a, int tile, const TileScratch& ts,
+                                          char* lds_base) {
+  constexpr int XS = RLDS ? XS_R : 3;  // LDS doubles per slot
+  constexpr bool DB = RLDS;         // two slot arrays (see TileLDS)
   const int N = a.n_atoms;
   const int ncell = a.nc * a.nc * a.nc;
-  const TileLDS L = carve_lds(lds_base, N, ncell, RLDS, HALF);
+  TileLDS L = carve_lds(lds_base, N, ncell, RLDS, HALF);
   const int64_t n0 = (int64_t)tile * a.tile;
   const int64_t n1 = min(n0 + (int64_t)a.tile, a.n_steps);
   const size_t slice = (size_t)3 * N;
   const bool grad = (a.mode & MODE_GRAD) != 0;
+  const bool excess = (a.mode & MODE_EXCESS) != 0;
   const int B = blockDim.x;
   const int lane = threadIdx.x & (WAVE - 1);
   const int part = lane >> 5;  // list part of this lane (full lists)
@@ -642,52 +687,71 @@ __device__ void tile_body(const PathArgs& a, int tile, const TileScratch& ts, ch
   // rho_n of slot s, component c
   auto rho_get = [&](int s, int c) -> double {
     if constexpr (RLDS)
-      return L.X[6 * s + 3 + c];
+      return L.X[XS * s + 3 + c];
     else
       return ts.rglob[3 * s + c];
   };
   auto rho_set = [&](int s, int c, double v) {
     if constexpr (RLDS)
-      L.X[6 * s + 3 + c] = v;
+      L.X[XS * s + 3 + c] = v;
     else
       ts.rglob[3 * s + c] = v;
   };
+  // Loads slice m into slot array X (slot order of the current lists) and
+  // raises flag[m & 1] when an atom is more than skin/2 away from where the
+  // lists were built (then slice m needs new lists).
+  auto load_slice = [&](lds_f64* X, int64_t m) {
+    double dmax = 0.0;
+    for (int s = threadIdx.x; s < N; s += B) {
+      const int o = L.perm[s];
+      double d2 = 0.0;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const double u = a.x[(size_t)m * slice + (size_t)c * N + o] * ib;
+        X[XS * s + c] = u;
+        const double du = wrap_u(u - ts.xref[3 * s + c]);
+        d2 = fma(du, du, d2);
+      }
+      dmax = fmax(dmax, d2);
+    }
+    if (!(dmax <= a.bu.half_skin2)) L.flag[m & 1] = 1;
+  };
 
+  // The tile's first lists are built from its middle slice: every slice of
+  // the tile is then at most half a tile away from the build positions, which
+  // keeps atoms within skin/2 of them for twice as many steps as lists built
+  // at the tile's first slice.
+  const int64_t nref = n0 + (n1 - n0) / 2;
   for (int i = threadIdx.x; i < N; i += B) {
-    L.perm[i] = i;
+    L.perm[i] = (uint16_t)i;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      L.X[XS * i + c] = a.x[(size_t)n0 * slice + (size_t)c * N + i] * ib;
+      L.X[XS * i + c] = a.x[(size_t)nref * slice + (size_t)c * N + i] * ib;
       ts.rprev[3 * i + c] = 0.0;
     }
   }
-  bool need_build = true;
+  if (threadIdx.x == 0) L.flag[0] = L.flag[1] = 0;
+  bool first = true;  // X holds the middle slice, whose lists come first
 
-  for (int64_t n = n0; n < n1; ++n) {
+  for (int64_t n = n0; n < n1;) {
+    __syncthreads();  // X holds x_n (or the middle slice); flag[n & 1] is final
+    if (first || L.flag[n & 1]) {
+      rebuild<XS, HALF>(a, L, ts);
+      __syncthreads();  // lists and slots ready
+      if (first) {
+        // x_n0 in the new slot order; it may itself need new lists
+        first = false;
+        load_slice(L.X, n0);
+        continue;
+      }
+    }
     const double w = a.weights ? a.weights[n] : 1.0;
     const double* xcur = a.x + (size_t)n * slice;
     const double* xnext = xcur + slice;
-    __syncthreads();  // X holds x_n
-
-    if (!need_build) {
-      double m = 0.0;
-      for (int s = threadIdx.x; s < N; s += B) {
-        const double ux = wrap_u(L.X[XS * s + 0] - ts.xref[3 * s + 0]);
-        const double uy = wrap_u(L.X[XS * s + 1] - ts.xref[3 * s + 1]);
-        const double uz = wrap_u(L.X[XS * s + 2] - ts.xref[3 * s + 2]);
-        m = fmax(m, fma(ux, ux, fma(uy, uy, uz * uz)));
-      }
-      m = block_max_all(m, L.red);
-      need_build = !(m <= a.bu.half_skin2);
-    }
-    if (need_build) {
-      rebuild<XS, HALF>(a, L, ts);
-      need_build = false;
-    }
-    if (HALF) {
+    if constexpr (HALF) {
       for (int e = threadIdx.x; e < 3 * N; e += B) L.ACC[e] = 0.0;
+      __syncthreads();  // ACC cleared
     }
-    __syncthreads();  // lists, slots and ACC ready
 
     // ---- pass 1: force, residual, per-step action ----
     double s_loc = 0.0, e_loc = 0.0;
@@ -733,19 +797,36 @@ __device__ void tile_body(const PathArgs& a, int tile, const TileScratch& ts, ch
         residual(s, f);
       }
     }
-    const double s_sum = block_sum(s_loc, L.red);
-    if (threadIdx.x == 0) a.per_step[n] = s_sum * a.inv4Ddt;
-    if (a.mode & MODE_EXCESS) {
-      const double e_sum = block_sum(e_loc, L.red);
-      if (threadIdx.x == 0) a.excess[n] = e_sum * a.inv4Ddt;
+    // per-wave partial sums; the block total is formed after the barrier
+    {
+      const double ws_ = wave_sum(s_loc);
+      const double we_ = excess ? wave_sum(e_loc) : 0.0;
+      if (lane == 0) {
+        L.red[wv] = ws_;
+        L.red[16 + wv] = we_;
+      }
     }
+    __syncthreads();  // rho_n of every atom is stored; partial sums are in red
+    if (threadIdx.x == 0) {
+      double t = 0.0;
+      for (int k = 0; k < nwv; ++k) t += L.red[k];
+      a.per_step[n] = t * a.inv4Ddt;
+      if (excess) {
+        double e = 0.0;
+        for (int k = 0; k < nwv; ++k) e += L.red[16 + k];
+        a.excess[n] = e * a.inv4Ddt;
+      }
+      L.flag[n & 1] = 0;  // every thread has read it; next raised by slice n + 2
+    }
+    // slice n + 1 goes into the other slot array while pass 2 reads this one
+    if (DB && n + 1 < n1) load_slice(L.X2, n + 1);
 
     // ---- pass 2: Hessian-vector product and gradient ----
     if (grad) {
-      if (HALF) {
+      if constexpr (HALF) {
         for (int e = threadIdx.x; e < 3 * N; e += B) L.ACC[e] = 0.0;
+        __syncthreads();  // ACC cleared
       }
-      __syncthreads();  // rho_n of every atom is stored; ACC cleared
       const double cq = a.c * a.mu_dt;
       if constexpr (!HALF) {
         for (int base = wv * 32; base < N; base += nwv * 32) {
@@ -754,7 +835,7 @@ __device__ void tile_body(const PathArgs& a, int tile, const TileScratch& ts, ch
           double q[3] = {0.0, 0.0, 0.0};
           if (live) {
             if constexpr (RLDS)
-              pass2_part<XS, 6, F32, false, 2>(a, L, L.X + 3, ts, s, part, 2 * s + part, 2 * N,
+              pass2_part<XS, XS, F32, false, 2>(a, L, L.X + 3, ts, s, part, 2 * s + part, 2 * N,
                                                q[0], q[1], q[2]);
             else
               pass2_part<XS, 3, F32, false, 2>(a, L, (const double*)ts.rglob, ts, s, part,
@@ -782,7 +863,7 @@ __device__ void tile_body(const PathArgs& a, int tile, const TileScratch& ts, ch
           q[kk][0] = q[kk][1] = q[kk][2] = 0.0;
           if (s < N) {
             if constexpr (RLDS)
-              pass2_part<XS, 6, F32, true, 1>(a, L, L.X + 3, ts, s, 0, s, N, q[kk][0], q[kk][1],
+              pass2_part<XS, XS, F32, true, 1>(a, L, L.X + 3, ts, s, 0, s, N, q[kk][0], q[kk][1],
                                               q[kk][2]);
             else
               pass2_part<XS, 3, F32, true, 1>(a, L, (const double*)ts.rglob, ts, s, 0, s, N,
@@ -807,12 +888,15 @@ __device__ void tile_body(const PathArgs& a, int tile, const TileScratch& ts, ch
         }
       }
     }
-    __syncthreads();  // every read of X (and rho, ACC) for slice n is done
-    for (int s = threadIdx.x; s < N; s += B) {
-      const int o = L.perm[s];
-#pragma unroll
-      for (int c = 0; c < 3; ++c) L.X[XS * s + c] = xnext[(size_t)c * N + o] * ib;
+    if constexpr (DB) {
+      lds_f64* t = L.X;
+      L.X = L.X2;
+      L.X2 = t;
+    } else if (n + 1 < n1) {
+      __syncthreads();  // every read of X (and rho, ACC) for slice n is done
+      load_slice(L.X, n + 1);
     }
+    ++n;
   }
 
   if (grad) {

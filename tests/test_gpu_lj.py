@@ -259,3 +259,40 @@ def test_lj864_fd_gradient_16_coordinates(device, lj864_full):
         fd = (vals[0] - vals[1]) / (2 * h)
         scale = max(abs(g[m, c, a]), 1e-3 * np.max(np.abs(g[m])))
         assert abs(fd - g[m, c, a]) <= 2e-5 * scale + 1e-6 * np.max(np.abs(g[m])), (m, c, a)
+
+
+# ---------------------------------------------------------------------------
+# Path-sampling size: 4000 atoms.  A slice does not fit the workgroup's LDS
+# with its residuals, so they live in global scratch and the cell grid is the
+# finest that fits; the oracle (cell-list mode) checks sampled slices.
+# ---------------------------------------------------------------------------
+def _check_sampled(w, X, S, s, g, picks):
+    assert np.all(s > 0) and np.all(np.isfinite(g))
+    assert rel(S, math.fsum(s.tolist())) <= 1e-13
+    pot = oracle_pot(w)
+    for m in picks:
+        sm, gm = OA.slice_terms(X, m, pot, w.dt, w.D, w.gamma, method="cells")
+        assert rel_inf(g[m], gm) <= GRAD_TOL, m
+        if sm is not None:
+            assert rel(s[m], sm) <= ACTION_TOL, m
+
+
+def test_lj4000_ragged_tiles_sampled(device):
+    w = W.workload("sweep4000").with_steps(100)
+    X = W.tethered_path(w)
+    S, s, g = run(w, X, tuning=P.make_tuning("fused", tile=32))
+    # tile edges (32, 64, 96), the ragged last tile (96..99) and both ends
+    _check_sampled(w, X, S, s, g, [0, 1, 31, 32, 33, 64, 95, 96, 99, 100])
+
+
+def test_sweep4000_full_size_sampled(device):
+    """The path-sampling workload at full size (4000 atoms x 16384 steps,
+    1.6 GB of coordinates) in the default launch configuration."""
+    w = W.workload("sweep4000")
+    X = W.tethered_path(w)
+    S, s, g = run(w, X)
+    tile = max(1, min(32, w.n_steps // 256))
+    rng = np.random.default_rng(w.seed + 11)
+    picks = {0, tile - 1, tile, w.n_steps - 1, w.n_steps}
+    picks |= set(int(v) for v in rng.integers(0, w.n_steps + 1, size=3))
+    _check_sampled(w, X, S, s, g, sorted(picks))
