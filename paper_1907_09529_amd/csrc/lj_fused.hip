@@ -52,11 +52,9 @@ constexpr int EX_PAD = 32;     // exact-list entries per atom beyond kmax (see T
 // XS_R = 7 doubles, its position u (0..2), rho (3..5) and one unused, so that
 // pass 2 reads both from one address, and there are two slot arrays: slice
 // n + 1 is loaded into one while pass 2 of slice n reads the other.  The
-// 56-byte stride (14 four-byte banks) spreads the slots of either parity over
-// as many LDS banks as a 48-byte stride spreads all slots; each lane reads
-// partners of one slot parity (see rebuild).  Otherwise a slot holds 3
-// doubles (positions only; rho lives in global scratch) and there is one
-// array.
+// 56-byte stride (14 four-byte banks) spreads neighbouring positions over
+// twice as many LDS banks as a 48-byte one.  Otherwise a slot holds 3 doubles
+// (positions only; rho lives in global scratch) and there is one array.
 constexpr int XS_R = 7;
 struct TileLDS {
   lds_f64* X;     // stride XS: slice x_n / L, sorted slots (the array in use)
@@ -74,6 +72,13 @@ struct TileLDS {
   lds_i32* fill;  // build: ncell
   lds_u16* perm2; // build: n_atoms, scratch for re-sorting
   lds_u16* atoms; // build: n_atoms, slots in cell order
+  // LDS position of slot t.  With full lists the even slots come first and
+  // the odd ones after them (H = number of even slots): each lane reads
+  // partners of one slot parity, which then sit at consecutive positions and
+  // spread over all LDS banks.  Half lists keep slot order (H = 0).  List
+  // entries hold positions.
+  int H;
+  __device__ __forceinline__ int pos(int t) const { return H ? (t >> 1) + (t & 1) * H : t; }
 };
 
 // Shared-memory bytes of one tile (see carve_lds).
@@ -113,6 +118,7 @@ __device__ inline TileLDS carve_lds(char* base_generic, int n_atoms, int ncell, 
   t.fill = t.start + ncell + 1;
   t.perm2 = (lds_u16*)(t.fill + ncell);
   t.atoms = t.perm2 + n_atoms;
+  t.H = half ? 0 : (n_atoms + 1) / 2;
   return t;
 }
 
@@ -169,18 +175,19 @@ __device__ __forceinline__ int cell_of_slot(const lds_f64* X, int s, int nc) {
 // keep their slot order, so the result does not depend on thread timing.
 template <int XS>
 __device__ void sort_cells(int N, int nc, const TileLDS& L) {
+  auto cell = [&](int s) { return cell_of_slot<XS>(L.X, L.pos(s), nc); };
   const int ncell = nc * nc * nc;
   const int B = blockDim.x;
   for (int c = threadIdx.x; c < ncell; c += B) L.start[c] = 0;
   __syncthreads();
   for (int s = threadIdx.x; s < N; s += B)
-    atomicAdd((int*)&L.start[cell_of_slot<XS>(L.X, s, nc)], 1);
+    atomicAdd((int*)&L.start[cell(s)], 1);
   __syncthreads();
   block_exclusive_scan(L.start, ncell, L.tmp);
   for (int c = threadIdx.x; c < ncell; c += B) L.fill[c] = L.start[c];
   __syncthreads();
   for (int s = threadIdx.x; s < N; s += B)
-    L.atoms[atomicAdd((int*)&L.fill[cell_of_slot<XS>(L.X, s, nc)], 1)] = (uint16_t)s;
+    L.atoms[atomicAdd((int*)&L.fill[cell(s)], 1)] = (uint16_t)s;
   __syncthreads();
   for (int c = threadIdx.x; c < ncell; c += B) {
     const int lo = L.start[c], hi = L.start[c + 1];
@@ -219,24 +226,26 @@ __device__ void rebuild(const PathArgs& a, const TileLDS& L, const TileScratch& 
     // (dead at this point) when rho is in LDS, else global scratch
     for (int s = threadIdx.x; s < N; s += B) {
       const int old = L.atoms[s];
+      const int ps = L.pos(s), po = L.pos(old);
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        const double v = L.X[XS * old + c];
+        const double v = L.X[XS * po + c];
         if constexpr (XS == XS_R)
-          L.X[XS * s + 3 + c] = v;
+          L.X[XS * ps + 3 + c] = v;
         else
-          ts.rglob[3 * s + c] = v;
+          ts.rglob[3 * ps + c] = v;
       }
       L.perm2[s] = L.perm[old];
     }
     __syncthreads();
     for (int s = threadIdx.x; s < N; s += B) {
+      const int ps = L.pos(s);
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         if constexpr (XS == XS_R)
-          L.X[XS * s + c] = L.X[XS * s + 3 + c];
+          L.X[XS * ps + c] = L.X[XS * ps + 3 + c];
         else
-          L.X[XS * s + c] = ts.rglob[3 * s + c];
+          L.X[XS * ps + c] = ts.rglob[3 * ps + c];
       }
       L.perm[s] = L.perm2[s];
     }
@@ -262,7 +271,8 @@ __device__ void rebuild(const PathArgs& a, const TileLDS& L, const TileScratch& 
     const int s = base + (lane % SPAN);
     const bool live = s < N;
     const int sc = live ? s : base;
-    const double xs = L.X[XS * sc], ys = L.X[XS * sc + 1], zs = L.X[XS * sc + 2];
+    const int me = L.pos(sc);
+    const double xs = L.X[XS * me], ys = L.X[XS * me + 1], zs = L.X[XS * me + 2];
     uint16_t* nb = ts.nbr;
     const uint32_t wbase = 8u * (uint32_t)(PARTS * sc + part);
     const uint32_t wcap = wbase + cap;
@@ -275,37 +285,47 @@ __device__ void rebuild(const PathArgs& a, const TileLDS& L, const TileScratch& 
       over |= !room;
       woff += room ? ((woff & 7u) == 7u ? step8 : 1u) : 0u;
     };
-    // Candidates [t0, t1) are wave-uniform.  Each lane tests those of its
-    // parity in groups of up to 32, collecting the accepted ones in a bit
-    // mask, then appends them in a short loop over the set bits, so the test
-    // loop itself has no stores and no branches.
+    // Candidates are the slots [t0, t1) (wave-uniform).  Each lane tests
+    // those of its parity, which sit at consecutive LDS positions [p0,
+    // p0 + np), in groups of up to 32, collecting the accepted ones in a bit
+    // mask, then appends their positions in a short loop over the set bits,
+    // so the test loop itself has no stores and no branches.
     auto scan = [&](int t0, int t1) {
       t0 = __builtin_amdgcn_readfirstlane(t0);
       t1 = __builtin_amdgcn_readfirstlane(t1);
-      // candidate of lane-part p at position j of a group starting at g:
-      // g + PARTS * j + q, with q chosen so that its slot parity is p
-      const int q = PARTS == 1 ? 0 : ((part - t0) & 1);
-      for (int g = t0; g < t1; g += 32 * PARTS) {
+      int p0, np, nmax;
+      if constexpr (PARTS == 1) {
+        p0 = t0;
+        np = nmax = t1 - t0;
+      } else {
+        const int e0 = (t0 + 1) >> 1, e1 = (t1 + 1) >> 1;  // even slots 2k: k in [e0, e1)
+        const int o0 = t0 >> 1, o1 = t1 >> 1;              // odd slots 2k + 1: k in [o0, o1)
+        p0 = part ? L.H + o0 : e0;
+        np = part ? o1 - o0 : e1 - e0;
+        nmax = max(e1 - e0, o1 - o0);
+      }
+      const int plast = max(p0 + np - 1, 0);  // in-range position for padded lanes
+      for (int g = 0; g < nmax; g += 32) {
         uint32_t bits = 0;
         for (int j = 0; j < 32; j += 4) {
-          if (g + PARTS * j >= t1) break;
+          if (g + j >= nmax) break;
           double px[4], py[4], pz[4];
 #pragma unroll
           for (int u = 0; u < 4; ++u) {
-            const int t = min(g + PARTS * (j + u) + q, t1 - 1);
-            px[u] = L.X[XS * t + 0];
-            py[u] = L.X[XS * t + 1];
-            pz[u] = L.X[XS * t + 2];
+            const int p = min(p0 + g + j + u, plast);
+            px[u] = L.X[XS * p + 0];
+            py[u] = L.X[XS * p + 1];
+            pz[u] = L.X[XS * p + 2];
           }
 #pragma unroll
           for (int u = 0; u < 4; ++u) {
-            const int t = g + PARTS * (j + u) + q;
+            const int k = g + j + u;
             const double dx = wrap_u(xs - px[u]);
             const double dy = wrap_u(ys - py[u]);
             const double dz = wrap_u(zs - pz[u]);
             const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
-            const bool pass = t < t1 && t != s && r2 <= rl2 &&
-                              (!HALF || upper_half(dx, dy, dz, s, t));
+            const bool pass = k < np && p0 + k != me && r2 <= rl2 &&
+                              (!HALF || upper_half(dx, dy, dz, s, p0 + k));
             bits |= pass ? (1u << (j + u)) : 0u;
           }
         }
@@ -313,7 +333,7 @@ __device__ void rebuild(const PathArgs& a, const TileLDS& L, const TileScratch& 
         while (bits) {
           const int j = __builtin_ctz(bits);
           bits &= bits - 1u;
-          append(g + PARTS * j + q);
+          append(p0 + g + j);
         }
       }
     };
@@ -380,14 +400,14 @@ __device__ void rebuild(const PathArgs& a, const TileLDS& L, const TileScratch& 
       }
     }
     if (live) {
-      // pad the last chunk with the slot itself (read as invalid)
-      for (uint32_t o = woff; (o & 7u) != 0u; ++o) nb[o] = (uint16_t)s;
+      // pad the last chunk with the slot's own position (read as invalid)
+      for (uint32_t o = woff; (o & 7u) != 0u; ++o) nb[o] = (uint16_t)me;
       const uint32_t rel = woff - wbase;
       const int cnt = (int)((rel & ~7u) / (uint32_t)R + (rel & 7u));
       ts.cnt[PARTS * s + part] = over ? -1 : cnt;
       if (part == 0) {
 #pragma unroll
-        for (int c = 0; c < 3; ++c) ts.xref[3 * s + c] = L.X[XS * s + c];
+        for (int c = 0; c < 3; ++c) ts.xref[3 * s + c] = L.X[XS * me + c];
       }
     }
   }
@@ -464,12 +484,13 @@ __device__ __forceinline__ void for_each_listed(const uint16_t* list, int rows, 
 // Overflow scan (the list did not fit): atoms first, first + STEP, ... of the
 // slot's half (half lists) or of all other atoms (full lists).
 template <bool HALF, int STEP, typename Pair>
-__device__ __forceinline__ void for_each_atom(const PathArgs& a, const TileScratch& ts, int s,
-                                              int first, Pair&& pair) {
+__device__ __forceinline__ void for_each_atom(const PathArgs& a, const TileLDS& L,
+                                              const TileScratch& ts, int s, int first,
+                                              Pair&& pair) {
   for (int t = first; t < a.n_atoms; t += STEP) {
     if (t == s) continue;
     if (HALF && !ref_upper(ts.xref, s, t)) continue;
-    pair(t, true);
+    pair(L.pos(t), true);
   }
 }
 
@@ -485,7 +506,8 @@ __device__ __forceinline__ void pass1_part(const PathArgs& a, const TileLDS& L,
                                            int erows, double& fx, double& fy, double& fz) {
   const BoxUnits& k = a.bu;
   const int N = a.n_atoms;
-  const double xs = L.X[XS * s], ys = L.X[XS * s + 1], zs = L.X[XS * s + 2];
+  const int ps = L.pos(s);
+  const double xs = L.X[XS * ps], ys = L.X[XS * ps + 1], zs = L.X[XS * ps + 2];
   fx = fy = fz = 0.0;
   // accepted partners go to a 16-entry ring in LDS (a rejected entry's write
   // lands on the next free position and is overwritten); whole chunks of 8
@@ -562,12 +584,12 @@ __device__ __forceinline__ void pass1_part(const PathArgs& a, const TileLDS& L,
           flush(acc - done >= 4u);
         });
     if (acc > done) {  // pad the last chunk with the slot itself
-      for (uint32_t k = acc; k & 3u; ++k) ring[k & (STAGE - 1)] = (uint16_t)s;
+      for (uint32_t k = acc; k & 3u; ++k) ring[k & (STAGE - 1)] = (uint16_t)ps;
       flush(true);
     }
     L.ecnt[er] = (int16_t)acc;
   } else {
-    for_each_atom<HALF, STEP>(a, ts, s, part,
+    for_each_atom<HALF, STEP>(a, L, ts, s, part,
                               [&](int t, bool valid) { body(t, valid, std::false_type{}); });
     L.ecnt[er] = -1;
   }
@@ -583,8 +605,9 @@ __device__ __forceinline__ void pass2_part(const PathArgs& a, const TileLDS& L, 
                                            const TileScratch& ts, int s, int part, int er,
                                            int erows, double& qx, double& qy, double& qz) {
   const BoxUnits& k = a.bu;
-  const double xs = L.X[XS * s], ys = L.X[XS * s + 1], zs = L.X[XS * s + 2];
-  const double rx = R[RS * s], ry = R[RS * s + 1], rz = R[RS * s + 2];
+  const int ps = L.pos(s);
+  const double xs = L.X[XS * ps], ys = L.X[XS * ps + 1], zs = L.X[XS * ps + 2];
+  const double rx = R[RS * ps], ry = R[RS * ps + 1], rz = R[RS * ps + 2];
   qx = qy = qz = 0.0;
   auto body = [&](int t, bool valid, auto check) {
     const double dx = wrap_u(xs - L.X[XS * t + 0]);
@@ -662,7 +685,7 @@ __device__ __forceinline__ void pass2_part(const PathArgs& a, const TileLDS& L, 
         ts.ex, erows, er, ec, 0, [&](int t, bool valid) { body(t, valid, std::false_type{}); },
         [] {});
   else
-    for_each_atom<HALF, STEP>(a, ts, s, part,
+    for_each_atom<HALF, STEP>(a, L, ts, s, part,
                               [&](int t, bool valid) { body(t, valid, std::true_type{}); });
 }
 
@@ -687,15 +710,15 @@ __device__ __forceinline__ void tile_body(const PathArgs& a, int tile, const Til
   // rho_n of slot s, component c
   auto rho_get = [&](int s, int c) -> double {
     if constexpr (RLDS)
-      return L.X[XS * s + 3 + c];
+      return L.X[XS * L.pos(s) + 3 + c];
     else
-      return ts.rglob[3 * s + c];
+      return ts.rglob[3 * L.pos(s) + c];
   };
   auto rho_set = [&](int s, int c, double v) {
     if constexpr (RLDS)
-      L.X[XS * s + 3 + c] = v;
+      L.X[XS * L.pos(s) + 3 + c] = v;
     else
-      ts.rglob[3 * s + c] = v;
+      ts.rglob[3 * L.pos(s) + c] = v;
   };
   // Loads slice m into slot array X (slot order of the current lists) and
   // raises flag[m & 1] when an atom is more than skin/2 away from where the
@@ -703,12 +726,12 @@ __device__ __forceinline__ void tile_body(const PathArgs& a, int tile, const Til
   auto load_slice = [&](lds_f64* X, int64_t m) {
     double dmax = 0.0;
     for (int s = threadIdx.x; s < N; s += B) {
-      const int o = L.perm[s];
+      const int o = L.perm[s], ps = L.pos(s);
       double d2 = 0.0;
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         const double u = a.x[(size_t)m * slice + (size_t)c * N + o] * ib;
-        X[XS * s + c] = u;
+        X[XS * ps + c] = u;
         const double du = wrap_u(u - ts.xref[3 * s + c]);
         d2 = fma(du, du, d2);
       }
@@ -726,7 +749,7 @@ __device__ __forceinline__ void tile_body(const PathArgs& a, int tile, const Til
     L.perm[i] = (uint16_t)i;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      L.X[XS * i + c] = a.x[(size_t)nref * slice + (size_t)c * N + i] * ib;
+      L.X[XS * L.pos(i) + c] = a.x[(size_t)nref * slice + (size_t)c * N + i] * ib;
       ts.rprev[3 * i + c] = 0.0;
     }
   }
