@@ -94,18 +94,19 @@ class HipEvents:
         self.hip.hipEventDestroy(self.b)
 
 
-def cpu_baseline(X: np.ndarray, w, target_s: float = 12.0) -> dict:
+def cpu_baseline(X: np.ndarray, w, target_s: float = 12.0, method: str = "brute") -> dict:
     """The oracle (as written) on a bounded sample of the same path, all host cores."""
     import multiprocessing as mp
     cores = min(os.cpu_count() or 1, 16)
     t0 = time.perf_counter()
-    _oracle_chunk((X[0:3], w))
+    _oracle_chunk((X[0:3], w, method))
     t1 = time.perf_counter() - t0           # two slices of oracle work
     per_slice = max(t1 / 2.0, 1e-3)
     per_core = max(1, int(target_s / per_slice))
     n = min(per_core * cores, X.shape[0] - 2)
     bounds = np.linspace(0, n, cores + 1).astype(int)
-    chunks = [(X[bounds[c]:bounds[c + 1] + 1], w) for c in range(cores) if bounds[c + 1] > bounds[c]]
+    chunks = [(X[bounds[c]:bounds[c + 1] + 1], w, method) for c in range(cores)
+              if bounds[c + 1] > bounds[c]]
     t0 = time.perf_counter()
     with mp.get_context("fork").Pool(len(chunks)) as pool:
         done = sum(pool.map(_oracle_chunk, chunks))
@@ -118,7 +119,7 @@ def cpu_baseline(X: np.ndarray, w, target_s: float = 12.0) -> dict:
 
 
 def _oracle_chunk(args):
-    Xc, w = args
+    Xc, w, method = args
     from oracle import forces as OF
     from oracle.potentials import LennardJones
     pot = LennardJones(eps=w.eps, sigma=w.sigma, rc=w.cutoff, box=w.box)
@@ -127,9 +128,9 @@ def _oracle_chunk(args):
     count = 0
     for n in range(Xc.shape[0] - 1):
         d = OF.minimum_image(Xc[n + 1] - Xc[n], w.box)
-        r = d - mu * OF.forces(Xc[n], pot)
+        r = d - mu * OF.forces(Xc[n], pot, method)
         _ = np.sum(r * r) / (4.0 * w.D * w.dt)
-        q = OF.hessian_vec(Xc[n], r, pot)
+        q = OF.hessian_vec(Xc[n], r, pot, method)
         g = c * (-r + mu * q)
         if r_prev is not None:
             g += c * r_prev
@@ -138,13 +139,14 @@ def _oracle_chunk(args):
     return count
 
 
-def main(argv=None) -> int:
+def _parser():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--variant", choices=["fused", "plain", "fp32_force"], default="fused")
-    ap.add_argument("--workload", default="lj864")
+    ap.add_argument("--workload", default="lj864",
+                    help="lj864 (default), lj108, lj27, ho1d, batch64 or sweep4000")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--list", choices=["auto", "full", "half"], default="auto")
@@ -153,13 +155,49 @@ def main(argv=None) -> int:
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="after timing, run one device copy of this many MiB (for counter calibration)")
-    args = ap.parse_args(argv)
+    return ap
+
+
+def _line(metric_value, ms, args, dtype, config, roof, baseline):
+    out = {
+        "metric": "slice_atom_action_grad_evals_per_s",
+        "value": metric_value,
+        "unit": "slice_atom_evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": dtype,
+        "data": "synthetic",
+        "config": config,
+        "roofline": roof,
+    }
+    if baseline is not None:
+        out["cpu_baseline"] = baseline
+    print(json.dumps(out), flush=True)
+
+
+def main(argv=None) -> int:
+    args = _parser().parse_args(argv)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the time-sharded "
               "multi-GPU design is described in DESIGN.md and not built.", file=sys.stderr)
         return 2
-
+    if args.workload == "batch64":
+        return bench_batch(args)
+    if args.workload == "sweep4000":
+        return bench_sweep(args)
     w = W.workload(args.workload)
+    if w.potential == "harmonic":
+        return bench_harmonic(args, w)
+    return bench_path(args, w)
+
+
+def bench_path(args, w) -> int:
+    """One Lennard-Jones path: one step = one pamd_action_grad call."""
     print(f"[bench] generating {w.name}: {w.n_steps} steps x {w.n_atoms} atoms", file=sys.stderr,
           flush=True)
     X = W.tethered_path(w)
@@ -243,29 +281,232 @@ def main(argv=None) -> int:
             "kernel": "lj_fused_kernel" if args.variant != "plain" else "plain pipeline",
             "kernel_ms": k_ms, "flop_per_slice_atom": flop_unit, "pairs_per_atom": ppa,
             "hbm_algorithmic_GBps": BYTES_SLICE_ATOM * units / (k_ms * 1e-3) / 1e9}
-    out = {
-        "metric": "slice_atom_action_grad_evals_per_s",
-        "value": value,
-        "unit": "slice_atom_evals/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64" if precision == "fp64" else "f32_pair/f64_accum",
-        "data": "synthetic",
-        "config": {"workload": f"LJ {w.n_atoms} atoms x {w.n_steps} steps, rho 0.8442, T 1, "
-                               f"rc 2.5, dt 1e-4, {args.variant}",
-                   "neighbour_list": args.list,
-                   "n_atoms": w.n_atoms, "n_steps": w.n_steps, "variant": args.variant,
-                   "parallelism": "single GPU"},
-        "roofline": roof,
-    }
-    if baseline is not None:
-        out["cpu_baseline"] = baseline
-    print(json.dumps(out), flush=True)
+    config = {"workload": f"LJ {w.n_atoms} atoms x {w.n_steps} steps, rho {w.density}, T 1, "
+                          f"rc {w.cutoff:.4g}, dt {w.dt:g}, {args.variant}",
+              "neighbour_list": args.list,
+              "n_atoms": w.n_atoms, "n_steps": w.n_steps, "variant": args.variant,
+              "parallelism": "single GPU"}
+    _line(value, ms_per_step, args, "f64" if precision == "fp64" else "f32_pair/f64_accum",
+          config, roof, baseline)
+    return 0
+
+
+def bench_harmonic(args, w) -> int:
+    """The 1-D harmonic path: one step = one pamd_action_grad call (a single
+    streaming kernel; at this size its time is launch latency)."""
+    X = W.free_walk_path(w)
+    baseline = None
+    if not args.no_cpu_baseline:
+        from oracle import action as OA
+        from oracle.potentials import Harmonic
+        pot_o = Harmonic(k=w.k)
+        reps, t0 = 0, time.perf_counter()
+        while time.perf_counter() - t0 < 2.0:
+            OA.per_step_action(X, pot_o, w.dt, w.D, w.gamma)
+            OA.path_gradient(X, pot_o, w.dt, w.D, w.gamma)
+            reps += 1
+        dt = time.perf_counter() - t0
+        baseline = {"value": reps * w.n_steps * w.n_atoms / dt, "unit": "slice_atom_evals/s",
+                    "cores": 1, "kind": "oracle",
+                    "sample": f"whole path x {reps} repetitions (per-step terms + gradient), "
+                              f"1 process, {dt:.1f} s wall"}
+    import torch
+    import paper_1907_09529_amd as P
+    P.load()
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    path = P.make_path(w.n_steps, w.n_atoms, w.n_dim, w.dt, w.D, w.gamma, "fp64")
+    pot = P.make_potential("harmonic", k=w.k)
+    x = torch.from_numpy(X).to(dev)
+    grad = torch.empty_like(x)
+    act = torch.empty(1, dtype=torch.float64, device=dev)
+    per_step = torch.empty(w.n_steps, dtype=torch.float64, device=dev)
+    ws = P.workspace(P.pamd_workspace_size(path, pot))
+    stream = torch.cuda.current_stream()
+    lib = P.load()
+    for _ in range(args.warmup):
+        P.pamd_action_grad(path, pot, x, grad, action=act, per_step=per_step, ws=ws, stream=stream)
+    torch.cuda.synchronize()
+    events = [HipEvents() for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        lib.pamd_profile_events(events[k].a, events[k].b)
+        P.pamd_action_grad(path, pot, x, grad, action=act, per_step=per_step, ws=ws, stream=stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    k_ms = float(np.mean([e.elapsed_ms() for e in events]))
+    for e in events:
+        e.close()
+    ms = (t1 - t0) * 1e3 / args.steps
+    units = w.n_steps * w.n_atoms
+    dof = w.n_atoms * w.n_dim
+    # streaming kernel: reads x (N+1 slices), writes g (N+1 slices) and s_n (N)
+    nbytes = 8 * (2 * (w.n_steps + 1) * dof + w.n_steps)
+    roof = {"bound": "hbm", "achieved": nbytes / (k_ms * 1e-3) / 1e9, "peak": PEAK_HBM / 1e9,
+            "unit": "GB/s", "frac": nbytes / (k_ms * 1e-3) / PEAK_HBM, "traffic": None,
+            "kernel": "ho_kernel", "kernel_ms": k_ms, "bytes_per_launch": nbytes,
+            "note": "launch-latency bound at this size"}
+    config = {"workload": f"1-D harmonic path, k {w.k:g}, dt {w.dt:g}, {w.n_steps} steps",
+              "n_atoms": w.n_atoms, "n_steps": w.n_steps, "parallelism": "single GPU"}
+    _line(units / (ms * 1e-3), ms, args, "f64", config, roof, baseline)
+    return 0
+
+
+def _member_flops(X, w) -> float:
+    """Algorithmic flops per slice-atom of one LJ path (pairs counted on 2 slices)."""
+    ppa = pairs_per_atom(X, w.box, w.cutoff, n_sample=2)
+    return ppa * (FLOP_FORCE_PAIR + FLOP_HV_PAIR) + FLOP_SLICE_ATOM
+
+
+def bench_batch(args) -> int:
+    """The 64-path batch: one step = one replay of a captured graph holding one
+    persistent pamd_batch_action_grad launch over every member."""
+    members = W.batch_members()
+    arrays = [W.tethered_path(m) for m in members]
+    units = sum(m.n_steps * m.n_atoms for m in members)
+    flops = sum(_member_flops(X, m) * m.n_steps * m.n_atoms for X, m in zip(arrays, members))
+    baseline = None
+    if not args.no_cpu_baseline:
+        # the oracle on the largest member (same per-slice work as the GPU's)
+        big = max(range(len(members)), key=lambda p: members[p].n_atoms * members[p].n_steps)
+        baseline = cpu_baseline(arrays[big], members[big])
+        baseline["sample"] = f"member {big} ({members[big].n_atoms} atoms): " + baseline["sample"]
+    import torch
+    import paper_1907_09529_amd as P
+    P.load()
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    paths, pots = [], []
+    for m in members:
+        paths.append(P.make_path(m.n_steps, m.n_atoms, 3, m.dt, m.D, m.gamma, "fp64"))
+        pots.append(P.make_potential("lj", eps=m.eps, sigma=m.sigma, rc=m.cutoff, box=m.box))
+    b = P.PamdBatch(paths, pots)
+    buf = np.zeros(b.x_offsets[-1])
+    for p, X in enumerate(arrays):
+        buf[b.x_offsets[p]:b.x_offsets[p] + X.size] = X.ravel()
+    x = torch.from_numpy(buf).to(dev)
+    grad = torch.zeros_like(x)
+    act = torch.empty(len(members), dtype=torch.float64, device=dev)
+    b.prepare()
+    s = torch.cuda.Stream()
+    g = P.PamdGraph()
+    torch.cuda.synchronize()
+    with torch.cuda.stream(s):
+        g.begin(s)
+        b.pamd_batch_action_grad(x, act, grad_all=grad, stream=s)
+        g.end(s)
+        for _ in range(args.warmup):
+            g.launch(s)
+    s.synchronize()
+    ev = [HipEvents() for _ in range(2)]
+    hip = HipEvents.hip
+    t0 = time.perf_counter()
+    hip.hipEventRecord(ev[0].a, ctypes.c_void_p(s.cuda_stream))
+    for _ in range(args.steps):
+        g.launch(s)
+    hip.hipEventRecord(ev[0].b, ctypes.c_void_p(s.cuda_stream))
+    s.synchronize()
+    t1 = time.perf_counter()
+    ms = (t1 - t0) * 1e3 / args.steps
+    g_ms = ev[0].elapsed_ms() / args.steps
+    for e in ev:
+        e.close()
+    g.close()
+    roof = {"bound": "alu", "achieved": flops / (g_ms * 1e-3) / 1e12, "peak": PEAK_FP64_VALU / 1e12,
+            "unit": "TFLOP/s", "frac": flops / (g_ms * 1e-3) / PEAK_FP64_VALU, "traffic": None,
+            "kernel": "graph replay (lj_batch_kernel + batch_finalize_kernel)", "kernel_ms": g_ms,
+            "flop_per_launch": flops}
+    config = {"workload": f"batch of {len(members)} LJ paths, atoms in {{108..2048}}, "
+                          f"steps {min(m.n_steps for m in members)}..{max(m.n_steps for m in members)}, "
+                          "one persistent launch, graph-captured",
+              "n_paths": len(members), "slice_atoms": units, "parallelism": "single GPU"}
+    _line(units / (ms * 1e-3), ms, args, "f64", config, roof, baseline)
+    return 0
+
+
+def bench_sweep(args) -> int:
+    """The path-sampling sweep (4000 atoms x 16384 steps): one step = one sweep,
+    a fragment-wise Metropolis-Hastings move (trial bridges, excess action of
+    the trial path, accept/commit) followed by action + gradient of the
+    committed path, replayed from a captured graph."""
+    w = W.workload("sweep4000")
+    print(f"[bench] generating {w.name}: {w.n_steps} steps x {w.n_atoms} atoms", file=sys.stderr,
+          flush=True)
+    X = W.tethered_path(w)
+    baseline = None
+    if not args.no_cpu_baseline:
+        baseline = cpu_baseline(X, w, target_s=12.0, method="cells")
+    flop_unit = _member_flops(X, w)
+    import torch
+    import paper_1907_09529_amd as P
+    P.load()
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    path = P.make_path(w.n_steps, w.n_atoms, 3, w.dt, w.D, w.gamma, "fp64")
+    pot = P.make_potential("lj", eps=w.eps, sigma=w.sigma, rc=w.cutoff, box=w.box)
+    x = torch.from_numpy(X).to(dev)
+    del X
+    trial = torch.empty_like(x)
+    grad = torch.empty_like(x)
+    ex = torch.empty(w.n_steps, dtype=torch.float64, device=dev)
+    act = torch.empty(1, dtype=torch.float64, device=dev)
+    counter = torch.zeros(1, dtype=torch.int64, device=dev)
+    info = torch.empty(4, dtype=torch.int32, device=dev)
+    ws_mh = P.workspace(P.pamd_mh_workspace_size(path, pot))
+    ws = P.workspace(P.pamd_workspace_size(path, pot))
+    P.pamd_excess_action(path, pot, x, ex)
+    s = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    seed = 0x5EED1907
+
+    def sweep(stream):
+        P.pamd_mh_step(path, pot, seed, w.l_min, w.l_max, counter, x, ex, trial,
+                       step_info=info, ws=ws_mh, stream=stream)
+        P.pamd_action_grad(path, pot, x, grad, action=act, ws=ws, stream=stream)
+
+    g = P.PamdGraph()
+    with torch.cuda.stream(s):
+        g.begin(s)
+        sweep(s)
+        g.end(s)
+        for _ in range(args.warmup):
+            g.launch(s)
+    s.synchronize()
+    ev = HipEvents()
+    hip = HipEvents.hip
+    t0 = time.perf_counter()
+    hip.hipEventRecord(ev.a, ctypes.c_void_p(s.cuda_stream))
+    for _ in range(args.steps):
+        g.launch(s)
+    hip.hipEventRecord(ev.b, ctypes.c_void_p(s.cuda_stream))
+    s.synchronize()
+    t1 = time.perf_counter()
+    ms = (t1 - t0) * 1e3 / args.steps
+    g_ms = ev.elapsed_ms() / args.steps
+    ev.close()
+    g.close()
+    # the action+gradient kernel alone, timed eagerly after the sweeps
+    lib = P.load()
+    kev = [HipEvents() for _ in range(3)]
+    for e in kev:
+        lib.pamd_profile_events(e.a, e.b)
+        P.pamd_action_grad(path, pot, x, grad, action=act, ws=ws, stream=torch.cuda.current_stream())
+    k_ms = float(np.mean([e.elapsed_ms() for e in kev]))
+    for e in kev:
+        e.close()
+    sweeps = int(counter.item())
+    units = w.n_steps * w.n_atoms
+    roof = {"bound": "alu", "achieved": flop_unit * units / (k_ms * 1e-3) / 1e12,
+            "peak": PEAK_FP64_VALU / 1e12, "unit": "TFLOP/s",
+            "frac": flop_unit * units / (k_ms * 1e-3) / PEAK_FP64_VALU, "traffic": None,
+            "kernel": "lj_fused_kernel (action + gradient, residuals in global scratch)",
+            "kernel_ms": k_ms, "flop_per_slice_atom": flop_unit, "sweep_ms": g_ms}
+    config = {"workload": f"path-sampling sweep, LJ {w.n_atoms} atoms x {w.n_steps} steps, "
+                          f"levels {w.l_min}..{w.l_max}, MH move + action + gradient per sweep, "
+                          "graph-captured",
+              "n_atoms": w.n_atoms, "n_steps": w.n_steps, "sweeps_run": sweeps,
+              "parallelism": "single GPU"}
+    _line(units / (ms * 1e-3), ms, args, "f64", config, roof, baseline)
     return 0
 
 

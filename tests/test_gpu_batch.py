@@ -79,3 +79,34 @@ def test_batch64_full_workload(device):
         for m in sorted({0, int(rng.integers(1, w.n_steps)), w.n_steps}):
             _, gm = OA.slice_terms(X, m, pot, w.dt, w.D, w.gamma)
             assert rel_inf(gp[m], gm) <= 1e-10, (p, m)
+
+
+def test_batch_graph_replays_match_eager(device):
+    """The persistent batched launch captured once and replayed, with eager work
+    and synchronisations between replays: every replay equals the eager result."""
+    members = [em_input("lj108", n_steps=40), em_input("lj108", n_atoms=256, n_steps=13),
+               em_input("ho1d", n_steps=50)]
+    paths, pots = zip(*(lib_descriptors(w) for w, _ in members))
+    b = P.PamdBatch(list(paths), list(pots))
+    x = pack(b, [X for _, X in members])
+    ref_g = torch.zeros_like(x)
+    ref_a = torch.empty(len(members), dtype=torch.float64, device="cuda")
+    b.pamd_batch_action_grad(x, ref_a, grad_all=ref_g)
+    torch.cuda.synchronize()
+    grad = torch.zeros_like(x)
+    act = torch.empty_like(ref_a)
+    s = torch.cuda.Stream()
+    g = P.PamdGraph()
+    with torch.cuda.stream(s):
+        g.begin(s)
+        b.pamd_batch_action_grad(x, act, grad_all=grad, stream=s)
+        g.end(s)
+    for _ in range(3):
+        grad.zero_()
+        act.zero_()
+        torch.cuda.synchronize()
+        with torch.cuda.stream(s):
+            g.launch(s)
+        s.synchronize()
+        assert torch.equal(act, ref_a) and torch.equal(grad, ref_g)
+    g.close()

@@ -104,3 +104,67 @@ def test_mh_graph_replay_advances_sweeps(device):
     assert int(counter.item()) == 4
     assert torch.equal(x, xe) and torch.equal(ex, exe)
     g.close()
+
+
+def test_sweep4000_full_size_graph(device):
+    """The path-sampling workload at full size (4000 atoms x 16384 steps): two
+    graph-replayed sweeps (MH move, then action + gradient of the committed
+    path).  Checked: the sweep counter, the move's bookkeeping, that only
+    accepted fragments changed, the carried excess action against a fresh
+    evaluation, and sampled gradient rows against the oracle."""
+    import workloads as W
+    from oracle import action as OA
+    w = W.workload("sweep4000")
+    X0 = W.tethered_path(w)
+    path, pot = lib_descriptors(w)
+    x = torch.from_numpy(X0).cuda()
+    ex = torch.empty(w.n_steps, dtype=torch.float64, device="cuda")
+    P.pamd_excess_action(path, pot, x, ex)
+    trial = torch.empty_like(x)
+    grad = torch.empty_like(x)
+    act = torch.empty(1, dtype=torch.float64, device="cuda")
+    counter = torch.zeros(1, dtype=torch.int64, device="cuda")
+    info = torch.empty(4, dtype=torch.int32, device="cuda")
+    fa = torch.empty(w.n_steps + 2, dtype=torch.int32, device="cuda")
+    ws_mh = P.workspace(P.pamd_mh_workspace_size(path, pot))
+    ws = P.workspace(P.pamd_workspace_size(path, pot))
+    s = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    g = P.PamdGraph()
+    with torch.cuda.stream(s):
+        g.begin(s)
+        P.pamd_mh_step(path, pot, SEED, w.l_min, w.l_max, counter, x, ex, trial,
+                       frag_accept=fa, step_info=info, ws=ws_mh, stream=s)
+        P.pamd_action_grad(path, pot, x, grad, action=act, ws=ws, stream=s)
+        g.end(s)
+    X = X0
+    for sweep in range(2):
+        with torch.cuda.stream(s):
+            g.launch(s)
+        s.synchronize()
+        assert int(counter.item()) == sweep + 1
+        l, u, nf, na = info.cpu().tolist()
+        assert w.l_min <= l <= w.l_max and 1 <= u <= 2 ** l and nf >= 1
+        acc = fa.cpu().numpy()[:nf].astype(bool)
+        assert na == int(acc.sum())
+        Xn = x.cpu().numpy()
+        T = trial.cpu().numpy()
+        frags = OS.fragments(w.n_steps, l, u)
+        assert len(frags) == nf
+        for f, (a, b, nose) in enumerate(frags):
+            hi = b + 1 if nose else b  # the nose moves its endpoint too
+            src = T if acc[f] else X
+            assert np.array_equal(Xn[a + 1:hi], src[a + 1:hi]), (sweep, f)
+            assert np.array_equal(Xn[a], X[a]), (sweep, f)  # shared endpoints stay
+        X = Xn
+        fresh = torch.empty_like(ex)
+        P.pamd_excess_action(path, pot, x, fresh)
+        torch.cuda.synchronize()
+        scale = float(np.abs(ex.cpu().numpy()).sum())
+        assert np.max(np.abs(ex.cpu().numpy() - fresh.cpu().numpy())) <= 1e-10 * scale
+    pot_o = oracle_pot(w)
+    gp = grad.cpu().numpy()
+    for m in (0, 7777, w.n_steps):
+        _, gm = OA.slice_terms(X, m, pot_o, w.dt, w.D, w.gamma, method="cells")
+        assert rel_inf(gp[m], gm) <= 1e-10, m
+    g.close()

@@ -20,10 +20,10 @@ Einstein relation (Sec. II A, Eq. 1): gamma = 1/(beta D).
 from .configs import (WORKLOADS, Workload, BatchWorkload, SEED_BASE, workload, batch_members,
                       box_length, n_fcc_cells)
 from .generate import (fcc_lattice, cubic_lattice, initial_lattice, draw_noise, tethered_path,
-                       ho_noise, rng_for)
+                       ho_noise, free_walk_path, rng_for)
 
 __all__ = [
     "WORKLOADS", "Workload", "BatchWorkload", "SEED_BASE", "workload", "batch_members",
     "box_length", "n_fcc_cells", "fcc_lattice", "cubic_lattice", "initial_lattice", "draw_noise", "tethered_path", "ho_noise",
-    "rng_for",
+    "free_walk_path", "rng_for",
 ]

@@ -101,3 +101,17 @@ def tethered_path(w: Workload, n_steps: int | None = None, vib_sd: float = 0.08,
         u = rho * u + step_sd * rng.standard_normal(shape)
         out[t] = sites + u + w.perturb_sd * rng.standard_normal(shape)
     return out
+
+
+def free_walk_path(w: Workload, n_steps: int | None = None) -> np.ndarray:
+    """Force-free stand-in path, (N+1, n_dim, n_atoms): a Gaussian random walk
+    from the origin with per-step sd sqrt(2 D dt) (the free-diffusion step),
+    slices 1..N then perturbed by N(0, perturb_sd^2)."""
+    n = w.n_steps if n_steps is None else n_steps
+    step_sd = math.sqrt(2.0 * w.D * w.dt)
+    rng = rng_for(w, stream=7)
+    shape = (n, w.n_dim, w.n_atoms)
+    steps = step_sd * rng.standard_normal(shape)
+    out = np.zeros((n + 1, w.n_dim, w.n_atoms))
+    out[1:] = np.cumsum(steps, axis=0) + w.perturb_sd * rng.standard_normal(shape)
+    return out
