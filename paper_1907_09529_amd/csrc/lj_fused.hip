@@ -204,6 +204,36 @@ __device__ void sort_cells(int N, int nc, const TileLDS& L) {
   __syncthreads();
 }
 
+// Evens out the two rows of an atom (lanes l and l + 32 of a wave, rows
+// `mine` and `other` of a list in chunks of CH entries, entry k of row r at
+// [(k / CH) rows + r] CH + k % CH): the longer row moves the surplus from its
+// tail to the other row's tail, and both pad their new last chunks with
+// `pad`.  A wave runs as long as its longest row, so this shortens the wave
+// by up to half the difference.  Rows of length -1 (overflow) stay as they
+// are.  Every lane of the wave must call; `live` lanes take part.  (Used for
+// the neighbour lists at each build; evening out the exact lists every slice
+// costs more in pass 1 than it saves in pass 2.)
+template <int CH>
+__device__ __forceinline__ int balance_rows(uint16_t* list, int rows, int mine, int other_row,
+                                            int cnt, bool live, uint16_t pad) {
+  const int other = __shfl_xor(cnt, 32, WAVE);
+  if (!live || cnt < 0 || other < 0) return cnt;
+  const int k = (cnt - other) / 2;  // > 0: give k entries; < 0: receive -k
+  auto at = [&](int r, int e) { return ((size_t)(e / CH) * rows + r) * CH + e % CH; };
+  if (k > 0) {
+    for (int i = 0; i < k; ++i) list[at(other_row, other + i)] = list[at(mine, cnt - k + i)];
+    // the moved entries must not be read again from this row's last chunk
+    for (int e = cnt - k; e % CH; ++e) list[at(mine, e)] = pad;
+    return cnt - k;
+  }
+  if (k < 0) {
+    const int n = cnt - k;
+    for (int e = n; e % CH; ++e) list[at(mine, e)] = pad;
+    return n;
+  }
+  return cnt;
+}
+
 // Entries per list row: one row per atom for half lists; for full lists two
 // rows per atom (parts 0 and 1: partners of even and odd slot index), each
 // with room for half of kmax plus a spare chunk.
@@ -399,12 +429,17 @@ __device__ void rebuild(const PathArgs& a, const TileLDS& L, const TileScratch& 
         }
       }
     }
+    int cnt = 0;
     if (live) {
       // pad the last chunk with the slot's own position (read as invalid)
       for (uint32_t o = woff; (o & 7u) != 0u; ++o) nb[o] = (uint16_t)me;
       const uint32_t rel = woff - wbase;
-      const int cnt = (int)((rel & ~7u) / (uint32_t)R + (rel & 7u));
-      ts.cnt[PARTS * s + part] = over ? -1 : cnt;
+      cnt = over ? -1 : (int)((rel & ~7u) / (uint32_t)R + (rel & 7u));
+    }
+    if constexpr (PARTS == 2)
+      cnt = balance_rows<8>(nb, R, 2 * sc + part, 2 * sc + 1 - part, cnt, live, (uint16_t)me);
+    if (live) {
+      ts.cnt[PARTS * s + part] = cnt;
       if (part == 0) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) ts.xref[3 * s + c] = L.X[XS * me + c];
