@@ -44,18 +44,23 @@ typedef __attribute__((address_space(3))) double lds_f64;
 typedef __attribute__((address_space(3))) int lds_i32;
 typedef __attribute__((address_space(3))) uint16_t lds_u16;
 typedef __attribute__((address_space(3))) int16_t lds_i16;
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+typedef __attribute__((address_space(3))) f64x2 lds_f64x2;
+
+// 16-byte LDS load (ds_read_b128) of two doubles at a 16-byte aligned address.
+__device__ __forceinline__ f64x2 lds_ld2(const lds_f64* p) { return *(const lds_f64x2*)p; }
 
 constexpr int HALF_SLOTS = 2;  // atoms per thread supported by the half-list kernel
 constexpr int EX_PAD = 32;     // exact-list entries per atom beyond kmax (see TileScratch)
 
 // Shared-memory layout of one tile.  With rho in LDS every slot holds
-// XS_R = 7 doubles, its position u (0..2), rho (3..5) and one unused, so that
-// pass 2 reads both from one address, and there are two slot arrays: slice
-// n + 1 is loaded into one while pass 2 of slice n reads the other.  The
-// 56-byte stride (14 four-byte banks) spreads neighbouring positions over
-// twice as many LDS banks as a 48-byte one.  Otherwise a slot holds 3 doubles
-// (positions only; rho lives in global scratch) and there is one array.
-constexpr int XS_R = 7;
+// XS_R = 6 doubles, its position u (0..2) and rho (3..5), read as three
+// 16-byte loads, and there are two slot arrays: slice n + 1 is loaded into one
+// while pass 2 of slice n reads the other.  (16-byte LDS loads move about 1.6x
+// the bytes per clock of 8-byte ones at scattered addresses on gfx950.)
+// Otherwise a slot holds 3 doubles (positions only; rho lives in global
+// scratch) and there is one array.
+constexpr int XS_R = 6;
 struct TileLDS {
   lds_f64* X;     // stride XS: slice x_n / L, sorted slots (the array in use)
   lds_f64* X2;    // the other slot array (== X when there is one)
@@ -551,8 +556,17 @@ __device__ __forceinline__ void pass1_part(const PathArgs& a, const TileLDS& L,
   uint2* exr = reinterpret_cast<uint2*>(ts.ex) + er;
   uint32_t acc = 0, done = 0;  // entries accepted / stored
   auto body = [&](int t, bool valid, auto record) {
-    const double dx = wrap_u(xs - L.X[XS * t + 0]);
-    const double dy = wrap_u(ys - L.X[XS * t + 1]);
+    double ux, uy;  // partner position
+    if constexpr (XS == XS_R) {
+      const f64x2 uxy = lds_ld2(L.X + XS * t);
+      ux = uxy.x;
+      uy = uxy.y;
+    } else {
+      ux = L.X[XS * t + 0];
+      uy = L.X[XS * t + 1];
+    }
+    const double dx = wrap_u(xs - ux);
+    const double dy = wrap_u(ys - uy);
     const double dz = wrap_u(zs - L.X[XS * t + 2]);
     const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
     const bool ok = valid && r2 <= k.rc2;
@@ -645,13 +659,32 @@ __device__ __forceinline__ void pass2_part(const PathArgs& a, const TileLDS& L, 
   const double rx = R[RS * ps], ry = R[RS * ps + 1], rz = R[RS * ps + 2];
   qx = qy = qz = 0.0;
   auto body = [&](int t, bool valid, auto check) {
-    const double dx = wrap_u(xs - L.X[XS * t + 0]);
-    const double dy = wrap_u(ys - L.X[XS * t + 1]);
-    const double dz = wrap_u(zs - L.X[XS * t + 2]);
+    double px, py, pz, qtx, qty, qtz;  // partner position and rho
+    if constexpr (XS == XS_R && RS == XS_R) {
+      // one slot: u (0..2) and rho (3..5) as three 16-byte loads
+      const f64x2 a0 = lds_ld2(L.X + XS * t), a1 = lds_ld2(L.X + XS * t + 2),
+                  a2 = lds_ld2(L.X + XS * t + 4);
+      px = a0.x;
+      py = a0.y;
+      pz = a1.x;
+      qtx = a1.y;
+      qty = a2.x;
+      qtz = a2.y;
+    } else {
+      px = L.X[XS * t + 0];
+      py = L.X[XS * t + 1];
+      pz = L.X[XS * t + 2];
+      qtx = R[RS * t + 0];
+      qty = R[RS * t + 1];
+      qtz = R[RS * t + 2];
+    }
+    const double dx = wrap_u(xs - px);
+    const double dy = wrap_u(ys - py);
+    const double dz = wrap_u(zs - pz);
     const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
     bool ok = valid;
     if constexpr (decltype(check)::value) ok = ok && r2 <= k.rc2;
-    const double wx = rx - R[RS * t + 0], wy = ry - R[RS * t + 1], wz = rz - R[RS * t + 2];
+    const double wx = rx - qtx, wy = ry - qty, wz = rz - qtz;
     if constexpr (F32) {
       float iru = rsqrt_f32((float)r2);
       iru = ok ? iru : 0.0f;
