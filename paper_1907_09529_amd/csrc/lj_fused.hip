@@ -247,10 +247,11 @@ __device__ __forceinline__ int row_capacity(int kmax) {
   return HALF ? kmax : ((kmax / 2 + 15) & ~7);
 }
 
-// (Re)builds the neighbour lists of the slice in L.X.  With cells, atoms are
-// first re-sorted into cell order (slots and perm are rewritten).
+// (Re)builds the neighbour lists (radius^2 rl2, box units) of the slice in
+// L.X.  With cells, atoms are first re-sorted into cell order (slots and perm
+// are rewritten).
 template <int XS, bool HALF>
-__device__ void rebuild(const PathArgs& a, const TileLDS& L, const TileScratch& ts) {
+__device__ void rebuild(const PathArgs& a, const TileLDS& L, const TileScratch& ts, double rl2) {
   constexpr int PARTS = HALF ? 1 : 2;
   constexpr int SPAN = WAVE / PARTS;  // slots per wave
   const int N = a.n_atoms;
@@ -287,7 +288,6 @@ __device__ void rebuild(const PathArgs& a, const TileLDS& L, const TileScratch& 
     __syncthreads();
   }
   const int nc = a.nc, reach = a.reach;
-  const double rl2 = a.bu.rlist2;
   const int lane = threadIdx.x & (WAVE - 1);
   const int part = PARTS == 1 ? 0 : lane / SPAN;
   const int R = PARTS * N;  // list rows
@@ -788,9 +788,12 @@ __device__ __forceinline__ void tile_body(const PathArgs& a, int tile, const Til
     else
       ts.rglob[3 * L.pos(s) + c] = v;
   };
+  // This tile's displacement bound (hs2, squared) and list radius^2 (rl2),
+  // set below; box units.
+  double hs2 = a.bu.half_skin2, rl2 = a.bu.rlist2;
   // Loads slice m into slot array X (slot order of the current lists) and
-  // raises flag[m & 1] when an atom is more than skin/2 away from where the
-  // lists were built (then slice m needs new lists).
+  // raises flag[m & 1] when an atom has moved further than sqrt(hs2) from
+  // where the lists were built (then slice m needs new lists).
   auto load_slice = [&](lds_f64* X, int64_t m) {
     double dmax = 0.0;
     for (int s = threadIdx.x; s < N; s += B) {
@@ -805,7 +808,7 @@ __device__ __forceinline__ void tile_body(const PathArgs& a, int tile, const Til
       }
       dmax = fmax(dmax, d2);
     }
-    if (!(dmax <= a.bu.half_skin2)) L.flag[m & 1] = 1;
+    if (!(dmax <= hs2)) L.flag[m & 1] = 1;
   };
 
   // The tile's first lists are built from its middle slice: every slice of
@@ -822,12 +825,40 @@ __device__ __forceinline__ void tile_body(const PathArgs& a, int tile, const Til
     }
   }
   if (threadIdx.x == 0) L.flag[0] = L.flag[1] = 0;
+  // List radius for this tile.  D2, the largest squared displacement of any
+  // atom from the middle slice over the force-evaluated slices n0 .. n1 - 1
+  // (box units, the same arithmetic as load_slice's test), bounds how far a
+  // pair distance moves: lists of radius r_c + 2 sqrt(D2) hold every pair
+  // that comes within r_c anywhere in the tile, and no slice asks for new
+  // lists.  When D2 exceeds (skin/2)^2 the configured skin applies and slices
+  // that move further get new lists.
+  double d2max = 0.0;
+  for (int i = threadIdx.x; i < N; i += B) {
+    double ur[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) ur[c] = a.x[(size_t)nref * slice + (size_t)c * N + i] * ib;
+    for (int64_t m = n0; m < n1; ++m) {
+      double d2 = 0.0;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const double du = wrap_u(a.x[(size_t)m * slice + (size_t)c * N + i] * ib - ur[c]);
+        d2 = fma(du, du, d2);
+      }
+      d2max = fmax(d2max, d2);
+    }
+  }
+  d2max = block_max_all(d2max, L.red);
+  if (d2max <= hs2) {
+    hs2 = d2max;
+    const double r = sqrt(a.bu.rc2) + 2.0 * sqrt(d2max);
+    rl2 = r * r * (1.0 + 1e-12);
+  }
   bool first = true;  // X holds the middle slice, whose lists come first
 
   for (int64_t n = n0; n < n1;) {
     __syncthreads();  // X holds x_n (or the middle slice); flag[n & 1] is final
     if (first || L.flag[n & 1]) {
-      rebuild<XS, HALF>(a, L, ts);
+      rebuild<XS, HALF>(a, L, ts, rl2);
       __syncthreads();  // lists and slots ready
       if (first) {
         // x_n0 in the new slot order; it may itself need new lists
