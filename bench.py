@@ -16,6 +16,7 @@ from __future__ import annotations
 
 import argparse
 import ctypes
+import dataclasses
 import json
 import math
 import os
@@ -146,7 +147,8 @@ def _parser():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--variant", choices=["fused", "plain", "fp32_force"], default="fused")
     ap.add_argument("--workload", default="lj864",
-                    help="lj864 (default), lj108, lj27, ho1d, batch64 or sweep4000")
+                    help="lj864 (default), lj108, lj27, ho1d, batch64, sweep4000, "
+                         "em864 or em27 (sequential Euler-Maruyama integration)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--list", choices=["auto", "full", "half"], default="auto")
@@ -158,11 +160,12 @@ def _parser():
     return ap
 
 
-def _line(metric_value, ms, args, dtype, config, roof, baseline):
+def _line(metric_value, ms, args, dtype, config, roof, baseline,
+          metric="slice_atom_action_grad_evals_per_s", unit="slice_atom_evals/s"):
     out = {
-        "metric": "slice_atom_action_grad_evals_per_s",
+        "metric": metric,
         "value": metric_value,
-        "unit": "slice_atom_evals/s",
+        "unit": unit,
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
@@ -190,6 +193,8 @@ def main(argv=None) -> int:
         return bench_batch(args)
     if args.workload == "sweep4000":
         return bench_sweep(args)
+    if args.workload in ("em864", "em27"):
+        return bench_em(args, W.workload("lj" + args.workload[2:]))
     w = W.workload(args.workload)
     if w.potential == "harmonic":
         return bench_harmonic(args, w)
@@ -507,6 +512,146 @@ def bench_sweep(args) -> int:
               "n_atoms": w.n_atoms, "n_steps": w.n_steps, "sweeps_run": sweeps,
               "parallelism": "single GPU"}
     _line(units / (ms * 1e-3), ms, args, "f64", config, roof, baseline)
+    return 0
+
+
+# The paper's Lennard-Jones PAMD schedule with the largest speedup (Sec. IV B,
+# Simulation 2): N_path = 4096, levels 4..7, N_sample = 1 sweep per shift of
+# N_shift = 64 steps, dt = 2 dt_E.
+SIM2 = {"n_path": 4096, "l_min": 4, "l_max": 7, "n_sample": 1, "n_shift": 64, "dt_ratio": 2}
+EM_STEPS = 4096
+
+
+def _em_oracle_chunk(args):
+    x0, xi, w = args
+    from oracle import em as OE
+    from oracle.potentials import LennardJones
+    pot = LennardJones(eps=w.eps, sigma=w.sigma, rc=w.cutoff, box=w.box)
+    OE.em_path(x0, xi, pot, w.dt, w.D, w.gamma)
+    return xi.shape[0]
+
+
+def bench_em(args, w) -> int:
+    """Sequential Euler-Maruyama integration (Eq. 2) of one Lennard-Jones
+    system at dt_E = dt / 2: one step = one pamd_em_integrate call over 4096
+    time steps.  Also times one path-sampling sweep of the paper's Simulation 2
+    schedule on the same system and reports the measured counterpart of the
+    speedup chi (Eq. 20): the wall time of the N_shift dt / dt_E Euler steps
+    that one shifting event advances, over the N_sample sweeps it costs (the
+    shift itself is a ring-buffer offset and is not timed)."""
+    w_e = dataclasses.replace(w, dt=w.dt / SIM2["dt_ratio"], n_steps=EM_STEPS)
+    print(f"[bench] {w.name}: {EM_STEPS} Euler steps of {w.n_atoms} atoms at dt_E {w_e.dt:g}",
+          file=sys.stderr, flush=True)
+    x0 = W.initial_lattice(w.n_atoms, w.box)
+    xi, _ = W.draw_noise(w_e)
+    baseline = None
+    if not args.no_cpu_baseline:
+        import multiprocessing as mp
+        t0 = time.perf_counter()
+        _em_oracle_chunk((x0, xi[:2], w_e))
+        per_step = max((time.perf_counter() - t0) / 2.0, 1e-4)
+        cores = min(os.cpu_count() or 1, 16)
+        n = max(1, min(int(12.0 / per_step), EM_STEPS))
+        # a sequential chain cannot be split over cores: each process runs the
+        # same n steps and the rate is that of one chain
+        t0 = time.perf_counter()
+        with mp.get_context("fork").Pool(1) as pool:
+            done = pool.map(_em_oracle_chunk, [(x0, xi[:n], w_e)])[0]
+        dt = time.perf_counter() - t0
+        baseline = {"value": done * w.n_atoms / dt, "unit": "slice_atom_steps/s", "cores": 1,
+                    "kind": "oracle",
+                    "sample": f"{done} of {EM_STEPS} sequential Euler steps (brute-force pair "
+                              f"forces), one process ({cores} cores idle: the chain is serial), "
+                              f"{dt:.1f} s wall"}
+
+    import torch
+    import paper_1907_09529_amd as P
+    P.load()
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    pot = P.make_potential("lj", eps=w.eps, sigma=w.sigma, rc=w.cutoff, box=w.box)
+    path_e = P.make_path(EM_STEPS, w.n_atoms, 3, w_e.dt, w.D, w.gamma, "fp64")
+    x0_d = torch.from_numpy(x0).to(dev)
+    xi_d = torch.from_numpy(xi).to(dev)
+    del xi
+    out = torch.empty((EM_STEPS + 1, 3, w.n_atoms), dtype=torch.float64, device=dev)
+    ws = P.workspace(P.pamd_em_workspace_size(path_e, pot))
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        P.pamd_em_integrate(path_e, pot, x0_d, xi_d, out, ws=ws, stream=stream)
+    torch.cuda.synchronize()
+    lib = P.load()
+    events = [HipEvents() for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        lib.pamd_profile_events(events[k].a, events[k].b)
+        P.pamd_em_integrate(path_e, pot, x0_d, xi_d, out, ws=ws, stream=stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    k_ms = float(np.mean([e.elapsed_ms() for e in events]))
+    for e in events:
+        e.close()
+    ms = (t1 - t0) * 1e3 / args.steps
+    X_e = out.cpu().numpy()
+    ppa = pairs_per_atom(X_e, w.box, w.cutoff, n_sample=4)
+    flop_unit = ppa * 2 * FLOP_FORCE_PAIR + 12     # full lists: each pair evaluated twice
+    units = EM_STEPS * w.n_atoms
+    achieved = flop_unit * units / (k_ms * 1e-3)
+    peak_cu = PEAK_FP64_VALU / 256                 # one workgroup runs on one CU
+
+    # one sweep of the Simulation 2 schedule on a path of the same system,
+    # integrated at the PAMD step dt by the same integrator
+    sweep_ms = None
+    path_p = P.make_path(SIM2["n_path"], w.n_atoms, 3, w.dt, w.D, w.gamma, "fp64")
+    xi_p = torch.from_numpy(W.draw_noise(w.with_steps(SIM2["n_path"]))[0]).to(dev)
+    x = torch.empty((SIM2["n_path"] + 1, 3, w.n_atoms), dtype=torch.float64, device=dev)
+    P.pamd_em_integrate(path_p, pot, x0_d, xi_p, x,
+                        ws=P.workspace(P.pamd_em_workspace_size(path_p, pot)))
+    del xi_p
+    trial = torch.empty_like(x)
+    ex = torch.empty(SIM2["n_path"], dtype=torch.float64, device=dev)
+    counter = torch.zeros(1, dtype=torch.int64, device=dev)
+    ws_mh = P.workspace(P.pamd_mh_workspace_size(path_p, pot))
+    P.pamd_excess_action(path_p, pot, x, ex)
+    s = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    g = P.PamdGraph()
+    with torch.cuda.stream(s):
+        g.begin(s)
+        P.pamd_mh_step(path_p, pot, 0x5EED1907, SIM2["l_min"], SIM2["l_max"], counter, x, ex,
+                       trial, ws=ws_mh, stream=s)
+        g.end(s)
+        for _ in range(args.warmup):
+            g.launch(s)
+    s.synchronize()
+    ev = HipEvents()
+    n_sw = max(args.steps, 20)
+    HipEvents.hip.hipEventRecord(ev.a, ctypes.c_void_p(s.cuda_stream))
+    for _ in range(n_sw):
+        g.launch(s)
+    HipEvents.hip.hipEventRecord(ev.b, ctypes.c_void_p(s.cuda_stream))
+    s.synchronize()
+    sweep_ms = ev.elapsed_ms() / n_sw
+    ev.close()
+    g.close()
+    em_step_ms = k_ms / EM_STEPS
+    chi_paper = SIM2["n_shift"] * SIM2["dt_ratio"] / SIM2["n_sample"]
+    chi = SIM2["n_shift"] * SIM2["dt_ratio"] * em_step_ms / (SIM2["n_sample"] * sweep_ms)
+
+    roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": peak_cu / 1e12,
+            "unit": "TFLOP/s", "frac": achieved / peak_cu, "traffic": None,
+            "kernel": "lj_em_kernel (one workgroup; peak = one CU's FP64 VALU rate)",
+            "kernel_ms": k_ms, "flop_per_slice_atom": flop_unit, "pairs_per_atom": ppa}
+    config = {"workload": f"sequential Euler-Maruyama, LJ {w.n_atoms} atoms, rho {w.density}, "
+                          f"rc {w.cutoff:.4g}, {EM_STEPS} steps at dt_E {w_e.dt:g}",
+              "n_atoms": w.n_atoms, "n_steps": EM_STEPS, "em_step_us": em_step_ms * 1e3,
+              "sim2_sweep_ms": sweep_ms, "chi_paper": chi_paper, "chi_measured": chi,
+              "chi_note": "N_shift dt/dt_E Euler steps (wall) / N_sample graph-replayed sweeps "
+                          f"(N_path {SIM2['n_path']}, levels {SIM2['l_min']}..{SIM2['l_max']}) "
+                          "on this GPU",
+              "parallelism": "single GPU, one workgroup"}
+    _line(units / (ms * 1e-3), ms, args, "f64", config, roof, baseline,
+          metric="em_slice_atom_steps_per_s", unit="slice_atom_steps/s")
     return 0
 
 

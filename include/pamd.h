@@ -269,6 +269,30 @@ int pamd_mh_step(const pamd_path* path, const pamd_potential* pot, const pamd_tu
                  void* ws, size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------------------
+ * Sequential Euler-Maruyama integration (Eq. 2, Sec. II A): the time-stepping
+ * baseline that path sampling parallelises.  Steps
+ *     x_{n+1} = x_n + (dt / gamma) F(x_n) + sqrt(2 D dt) xi_n,   n = 0..N-1,
+ * in order, with the same forces (and, for Lennard-Jones, the same cell and
+ * neighbour lists) as the action kernels; coordinates stay unwrapped.  The
+ * action of the resulting path is sum_n |xi_n|^2 / 2 up to rounding.
+ * Lennard-Jones systems run as one workgroup stepping all atoms (float64
+ * forces, full neighbour lists: PAMD_FP32_FORCE, PAMD_LIST_HALF and
+ * PAMD_ALGO_PLAIN are rejected with PAMD_EUNSUPPORTED); harmonic systems run
+ * one thread per degree of freedom.  tuning->block and tuning->skin apply;
+ * tile and max_neighbours as for a one-step path.
+ * ---------------------------------------------------------------------- */
+int pamd_em_workspace_size(const pamd_path* path, const pamd_potential* pot,
+                           const pamd_tuning* tuning, size_t* bytes);
+
+/*   x0     device, n_dim * n_atoms float64: the first slice, layout of one slice
+ *   noise  device, N * n_dim * n_atoms float64: xi_n, layout of slices 0..N-1
+ *   x_out  device, (N + 1) * n_dim * n_atoms float64 (written: x_0 .. x_N);
+ *          must not overlap noise (x0 may be x_out's first slice) */
+int pamd_em_integrate(const pamd_path* path, const pamd_potential* pot,
+                      const pamd_tuning* tuning, const double* x0, const double* noise,
+                      double* x_out, void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
  * Autotuning: times candidate (block, tile, skin) choices for this problem on
  * the given inputs and caches the fastest for later calls with the same
  * (potential kind, n_atoms, cells per axis, precision) key.  Synchronises the
@@ -280,7 +304,7 @@ int pamd_autotune(const pamd_path* path, const pamd_potential* pot, const double
 
 /* ------------------------------------------------------------------------
  * Measurement hook: the next pamd_action / pamd_action_grad /
- * pamd_excess_action call made by this thread records `start` (a hipEvent_t)
+ * pamd_excess_action / pamd_em_integrate call made by this thread records `start` (a hipEvent_t)
  * on its stream just before its main kernel and `stop` just after it, so that
  * the events bracket that kernel alone.  Host-only; pass NULLs to clear.
  * ---------------------------------------------------------------------- */

@@ -83,6 +83,9 @@ _SIGNATURES = {
     "pamd_mh_step": (c_int32, [_PATH, _POT, _TUNE, c_uint64, c_int32, c_int32, c_void_p,
                                c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                                c_void_p, c_size_t, c_void_p]),
+    "pamd_em_workspace_size": (c_int32, [_PATH, _POT, _TUNE, POINTER(c_size_t)]),
+    "pamd_em_integrate": (c_int32, [_PATH, _POT, _TUNE, c_void_p, c_void_p, c_void_p, c_void_p,
+                                    c_size_t, c_void_p]),
     "pamd_autotune": (c_int32, [_PATH, _POT, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p,
                                 _TUNE]),
     "pamd_profile_events": (c_int32, [c_void_p, c_void_p]),

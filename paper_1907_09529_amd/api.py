@@ -22,7 +22,7 @@ __all__ = [
     "PamdPath", "PamdPotential", "PamdTuning", "PamdError", "make_path", "make_potential",
     "make_tuning", "pamd_workspace_size", "pamd_action", "pamd_action_grad",
     "pamd_excess_action", "pamd_log_norm", "pamd_mh_workspace_size", "pamd_mh_step",
-    "pamd_autotune", "PamdBatch", "PamdGraph", "workspace",
+    "pamd_em_workspace_size", "pamd_em_integrate", "pamd_autotune", "PamdBatch", "PamdGraph", "workspace",
 ]
 
 
@@ -148,6 +148,23 @@ def pamd_mh_step(path, pot, seed: int, l_min: int, l_max: int, sweep_counter: to
               _ptr(frag_delta, name="frag_delta"), _ptr(frag_accept, torch.int32, "frag_accept"),
               _ptr(step_info, torch.int32, "step_info"), _ptr(ws, None, "ws"),
               ctypes.c_size_t(ws.numel()), _stream(stream))
+
+
+# ---------------------------------------------------------------------------
+# sequential Euler-Maruyama integration
+# ---------------------------------------------------------------------------
+def pamd_em_workspace_size(path, pot, tuning=None) -> int:
+    n = ctypes.c_size_t(0)
+    _lib.call("pamd_em_workspace_size", ctypes.byref(path), ctypes.byref(pot), _ref(tuning),
+              ctypes.byref(n))
+    return int(n.value)
+
+
+def pamd_em_integrate(path, pot, x0, noise, x_out, ws=None, tuning=None, stream=None):
+    ws, _ = _ws(path, pot, tuning, ws, pamd_em_workspace_size)
+    _lib.call("pamd_em_integrate", ctypes.byref(path), ctypes.byref(pot), _ref(tuning),
+              _ptr(x0, name="x0"), _ptr(noise, name="noise"), _ptr(x_out, name="x_out"),
+              _ptr(ws, None, "ws"), ctypes.c_size_t(ws.numel()), _stream(stream))
 
 
 def pamd_autotune(path, pot, x, grad_scratch, ws, stream=None) -> PamdTuning:

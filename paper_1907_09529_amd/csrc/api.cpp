@@ -576,6 +576,71 @@ int pamd_mh_step(const pamd_path* p, const pamd_potential* v, const pamd_tuning*
 }
 
 // ---------------------------------------------------------------------------
+// Sequential Euler-Maruyama integration
+// ---------------------------------------------------------------------------
+}  // extern "C"
+
+namespace {
+// The integrator runs one workgroup: its plan is that of a one-step path (one
+// tile, scratch for one block).
+int em_plan(const pamd_path* p, const pamd_potential* v, const pamd_tuning* t, Plan& P) {
+  int rc;
+  if ((rc = check_path(p))) return rc;
+  pamd_path q = *p;
+  q.n_steps = 1;
+  if ((rc = make_plan(&q, v, t, false, P))) return rc;
+  if (v->kind == PAMD_LJ) {
+    if (P.algo != PAMD_ALGO_FUSED)
+      return fail(PAMD_EUNSUPPORTED, "the integrator uses the fused force pass (algo PLAIN given)");
+    if (P.f32) return fail(PAMD_EUNSUPPORTED, "the integrator computes forces in float64 only");
+    if (P.half) return fail(PAMD_EUNSUPPORTED, "the integrator uses full neighbour lists");
+  }
+  return PAMD_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int pamd_em_workspace_size(const pamd_path* p, const pamd_potential* v, const pamd_tuning* t,
+                           size_t* bytes) {
+  if (!bytes) return fail(PAMD_EINVAL, "bytes is NULL");
+  Plan P;
+  int rc = em_plan(p, v, t, P);
+  if (rc) return rc;
+  *bytes = P.total;
+  return PAMD_OK;
+}
+
+int pamd_em_integrate(const pamd_path* p, const pamd_potential* v, const pamd_tuning* t,
+                      const double* x0, const double* noise, double* x_out, void* ws,
+                      size_t ws_bytes, void* stream) {
+  Plan P;
+  int rc = em_plan(p, v, t, P);
+  if (rc) return rc;
+  if (!x0 || !noise || !x_out) return fail(PAMD_EINVAL, "x0, noise and x_out must be non-NULL");
+  const size_t dof = (size_t)P.dof;
+  const size_t nb = sizeof(double) * dof * (size_t)p->n_steps;
+  const char *nlo = (const char*)noise, *olo = (const char*)x_out;
+  if (nlo < olo + nb + sizeof(double) * dof && olo < nlo + nb)
+    return fail(PAMD_EINVAL, "x_out overlaps noise");
+  if ((rc = check_ws(P, ws, ws_bytes))) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  const double amp = std::sqrt(2.0 * p->D * p->dt);
+  EventScope ev(st);
+  if (v->kind == PAMD_HARMONIC) {
+    PAMD_HIP(launch_ho_em(x0, noise, x_out, p->n_steps, P.dof, v->k * p->dt / p->gamma, amp, st));
+    return PAMD_OK;
+  }
+  PathArgs a;
+  fill_lj(p, v, P, a);
+  a.n_steps = p->n_steps;
+  a.x = x0;
+  a.per_step = at<double>(ws, P.off_step);
+  PAMD_HIP(launch_lj_em(a, noise, amp, x_out, scratch_of(P, ws), launch_of(P), st));
+  return PAMD_OK;
+}
+
+// ---------------------------------------------------------------------------
 // Autotuning
 // ---------------------------------------------------------------------------
 int pamd_autotune(const pamd_path* p, const pamd_potential* v, const double* x,

@@ -54,6 +54,29 @@ __global__ void __launch_bounds__(256) ho_kernel(HOArgs a) {
   }
 }
 
+// Sequential Euler-Maruyama integration (Eq. 2) of the harmonic oscillator:
+// each thread steps one degree of freedom, x_{n+1} = x_n - (dt/gamma) k x_n +
+// sqrt(2 D dt) xi_n.
+__global__ void ho_em_kernel(const double* x0, const double* xi, double* xout, int64_t n_steps,
+                             int64_t n_dof, double kmu, double amp) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n_dof) return;
+  double x = x0[e];
+  xout[e] = x;
+  for (int64_t n = 0; n < n_steps; ++n) {
+    x = fma(amp, xi[n * n_dof + e], fma(-kmu, x, x));
+    xout[(n + 1) * n_dof + e] = x;
+  }
+}
+
+hipError_t launch_ho_em(const double* x0, const double* xi, double* xout, int64_t n_steps,
+                        int64_t n_dof, double kmu, double amp, hipStream_t st) {
+  const int64_t blocks = (n_dof + 255) / 256;
+  hipLaunchKernelGGL(ho_em_kernel, dim3((unsigned)blocks), dim3(256), 0, st, x0, xi, xout, n_steps,
+                     n_dof, kmu, amp);
+  return hipGetLastError();
+}
+
 hipError_t launch_ho(const HOArgs& a, double* action, hipStream_t st) {
   const int per_wave = WAVE / a.seg;
   const int64_t waves = (a.n_steps + 1 + per_wave - 1) / per_wave;

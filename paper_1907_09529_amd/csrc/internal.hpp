@@ -190,6 +190,12 @@ struct HOArgs {
   int32_t seg;     // lanes per slice in the reduction (power of two <= 64)
 };
 hipError_t launch_ho(const HOArgs& a, double* action, hipStream_t st);
+
+// Sequential Euler-Maruyama integrators (Eq. 2).
+hipError_t launch_lj_em(const PathArgs& a, const double* xi, double amp, double* xout,
+                        const BlockScratch& s, const FusedLaunch& L, hipStream_t st);
+hipError_t launch_ho_em(const double* x0, const double* xi, double* xout, int64_t n_steps,
+                        int64_t n_dof, double kmu, double amp, hipStream_t st);
 hipError_t launch_sum(const double* v, int64_t n, double* out, hipStream_t st);
 
 // Path sampling.

@@ -540,7 +540,8 @@ __device__ __forceinline__ void for_each_atom(const PathArgs& a, const TileLDS& 
 // row `er` of `erows` (ts.ex, padded with the slot itself to a whole chunk;
 // length in L.ecnt[er]) for pass 2; after an overflow scan no exact list is
 // recorded (-1).  With half lists the partners' shares are added into ACC.
-template <int XS, bool F32, bool HALF, int STEP>
+// REC = false computes the force alone (no exact list).
+template <int XS, bool F32, bool HALF, int STEP, bool REC = true>
 __device__ __forceinline__ void pass1_part(const PathArgs& a, const TileLDS& L,
                                            const TileScratch& ts, int s, int part, int er,
                                            int erows, double& fx, double& fy, double& fz) {
@@ -625,22 +626,28 @@ __device__ __forceinline__ void pass1_part(const PathArgs& a, const TileLDS& L,
   };
   const int cnt = ts.cnt[STEP * s + part];
   if (cnt >= 0) {
-    for_each_listed<8, 1>(
-        ts.nbr, STEP * N, STEP * s + part, cnt, 0,
-        [&](int t, bool valid) { body(t, valid, std::true_type{}); },
-        [&]() {
-          flush(acc - done >= 4u);
-          flush(acc - done >= 4u);
-        });
-    if (acc > done) {  // pad the last chunk with the slot itself
-      for (uint32_t k = acc; k & 3u; ++k) ring[k & (STAGE - 1)] = (uint16_t)ps;
-      flush(true);
+    if constexpr (REC) {
+      for_each_listed<8, 1>(
+          ts.nbr, STEP * N, STEP * s + part, cnt, 0,
+          [&](int t, bool valid) { body(t, valid, std::true_type{}); },
+          [&]() {
+            flush(acc - done >= 4u);
+            flush(acc - done >= 4u);
+          });
+      if (acc > done) {  // pad the last chunk with the slot itself
+        for (uint32_t k = acc; k & 3u; ++k) ring[k & (STAGE - 1)] = (uint16_t)ps;
+        flush(true);
+      }
+      L.ecnt[er] = (int16_t)acc;
+    } else {
+      for_each_listed<8, 1>(
+          ts.nbr, STEP * N, STEP * s + part, cnt, 0,
+          [&](int t, bool valid) { body(t, valid, std::false_type{}); }, [&]() {});
     }
-    L.ecnt[er] = (int16_t)acc;
   } else {
     for_each_atom<HALF, STEP>(a, L, ts, s, part,
                               [&](int t, bool valid) { body(t, valid, std::false_type{}); });
-    L.ecnt[er] = -1;
+    if constexpr (REC) L.ecnt[er] = -1;
   }
 }
 
@@ -1130,6 +1137,119 @@ __global__ void batch_finalize_kernel(const BatchMember* members, BatchBase base
   for (int64_t n = threadIdx.x; n < a.n_steps; n += blockDim.x) v += a.per_step[n];
   v = block_sum(v, red);
   if (threadIdx.x == 0) actions[slot[blockIdx.y]] = v;
+}
+
+// Sequential Euler-Maruyama integration (Eq. 2) of one Lennard-Jones system:
+// one workgroup steps x_{n+1} = x_n + (dt/gamma) F(x_n) + sqrt(2 D dt) xi_n
+// with the path kernel's force pass, slot layout and neighbour lists (new
+// lists when an atom has moved more than skin/2 since the last build).  x_n
+// in physical units is read back from x_out, where the previous step stored
+// it.  With DB the next slice goes straight into the second slot array;
+// otherwise it is reloaded from x_out after the step (one array, 3 doubles
+// per slot, sort scratch in global memory).
+template <bool DB>
+__global__ void __launch_bounds__(1024) lj_em_kernel(PathArgs a, const double* xi, double amp,
+                                                     double* xout, BlockScratch sc) {
+  extern __shared__ __align__(16) char lds[];
+  constexpr int XS = DB ? XS_R : 3;
+  const TileScratch ts = block_scratch(sc);
+  const int N = a.n_atoms;
+  TileLDS L = carve_lds(lds, N, a.nc * a.nc * a.nc, DB, false);
+  const size_t slice = (size_t)3 * N;
+  const double ib = a.lj.inv_box;
+  const int B = blockDim.x;
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int part = lane >> 5;
+  const int wv = threadIdx.x / WAVE, nwv = B / WAVE;
+  for (int i = threadIdx.x; i < N; i += B) {
+    L.perm[i] = (uint16_t)i;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const double v = a.x[(size_t)c * N + i];
+      xout[(size_t)c * N + i] = v;
+      L.X[XS * L.pos(i) + c] = v * ib;
+    }
+  }
+  if (threadIdx.x == 0) L.flag[0] = L.flag[1] = 0;
+  const double hs2 = a.bu.half_skin2, rl2 = a.bu.rlist2;
+  bool first = true;
+  for (int64_t n = 0; n < a.n_steps; ++n) {
+    __syncthreads();  // X and x_out hold x_n; flag[n & 1] is final
+    if (first || L.flag[n & 1]) {
+      rebuild<XS, false>(a, L, ts, rl2);
+      __syncthreads();  // lists and slots ready
+      first = false;
+    }
+    const double* xcur = xout + (size_t)n * slice;
+    double* xnext = xout + (size_t)(n + 1) * slice;
+    const double* xin = xi + (size_t)n * slice;
+    bool moved = false;
+    for (int base = wv * 32; base < N; base += nwv * 32) {
+      const int s = base + (lane & 31);
+      const bool live = s < N;
+      const bool own = live && part == 0;  // this lane steps atom perm[s]
+      // x_n and xi_n are fetched before the force pass so that their latency
+      // overlaps it
+      const int o = own ? (int)L.perm[s] : 0;
+      double xc[3] = {0.0, 0.0, 0.0}, xr[3] = {0.0, 0.0, 0.0};
+      if (own) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          xc[c] = xcur[(size_t)c * N + o];
+          xr[c] = xin[(size_t)c * N + o];
+        }
+      }
+      double f[3] = {0.0, 0.0, 0.0};
+      if (live)
+        pass1_part<XS, false, false, 2, false>(a, L, ts, s, part, 2 * s + part, 2 * N, f[0], f[1],
+                                               f[2]);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) f[c] += __shfl_xor(f[c], 32, WAVE);
+      if (own) {
+        double d2 = 0.0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const size_t e = (size_t)c * N + o;
+          const double x1 = fma(amp, xr[c], fma(a.mu_dt, f[c], xc[c]));
+          xnext[e] = x1;
+          const double u = x1 * ib;
+          if constexpr (DB) L.X2[XS * L.pos(s) + c] = u;
+          const double du = wrap_u(u - ts.xref[3 * s + c]);
+          d2 = fma(du, du, d2);
+        }
+        moved = moved || !(d2 <= hs2);
+      }
+    }
+    if (moved) L.flag[(n + 1) & 1] = 1;
+    __syncthreads();  // x_{n+1} is stored; every read of X for step n is done
+    if (threadIdx.x == 0) L.flag[n & 1] = 0;
+    if constexpr (DB) {
+      lds_f64* t = L.X;
+      L.X = L.X2;
+      L.X2 = t;
+    } else {
+      for (int s = threadIdx.x; s < N; s += B) {
+        const int o = L.perm[s];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) L.X[XS * L.pos(s) + c] = xnext[(size_t)c * N + o] * ib;
+      }
+    }
+  }
+}
+
+hipError_t launch_lj_em(const PathArgs& a, const double* xi, double amp, double* xout,
+                        const BlockScratch& s, const FusedLaunch& L, hipStream_t st) {
+  const void* k = L.r_in_lds ? (const void*)lj_em_kernel<true> : (const void*)lj_em_kernel<false>;
+  hipError_t e =
+      hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.lds_bytes);
+  if (e != hipSuccess) return e;
+  if (L.r_in_lds)
+    hipLaunchKernelGGL(lj_em_kernel<true>, dim3(1), dim3(L.block), L.lds_bytes, st, a, xi, amp,
+                       xout, s);
+  else
+    hipLaunchKernelGGL(lj_em_kernel<false>, dim3(1), dim3(L.block), L.lds_bytes, st, a, xi, amp,
+                       xout, s);
+  return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------

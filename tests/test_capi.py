@@ -205,3 +205,43 @@ def test_log_norm_matches_oracle():
 
 def test_graph_begin_rejects_null_stream():
     assert P.load().pamd_graph_begin(None) == _lib.PAMD_EINVAL
+
+
+def test_em_validation():
+    lib = P.load()
+
+    def size(path, pot, tuning=None):
+        n = ctypes.c_size_t(0)
+        code = lib.pamd_em_workspace_size(ctypes.byref(path), ctypes.byref(pot),
+                                          ctypes.byref(tuning) if tuning else None,
+                                          ctypes.byref(n))
+        return code, n.value
+
+    path, pot = lj_path(n_steps=1000), lj_pot()
+    code, need = size(path, pot)
+    assert code == 0 and need > 0 and need % 256 == 0
+    # one workgroup's scratch, whatever the path length
+    assert need == size(lj_path(n_steps=5), pot)[1]
+    assert need < ws_size(path, pot)[1]
+    assert size(path, pot, P.make_tuning("plain"))[0] == _lib.PAMD_EUNSUPPORTED
+    assert size(path, pot, P.make_tuning("fused", block=448, neighbour_list="half"))[0] == \
+        _lib.PAMD_EUNSUPPORTED
+    p32 = lj_path(n_steps=1000)
+    p32.precision = _lib.PAMD_FP32_FORCE
+    assert size(p32, pot)[0] == _lib.PAMD_EUNSUPPORTED
+    assert size(lj_path(n_steps=0), pot)[0] == _lib.PAMD_EINVAL
+    assert size(P.make_path(16, 2, 1, 0.01, 1.0, 1.0), P.make_potential("harmonic"))[0] == 0
+
+    def integrate(x0=FAKE, noise=ctypes.c_void_p(0x10000000), x_out=ctypes.c_void_p(0x20000000),
+                  ws=FAKE, ws_bytes=need):
+        return lib.pamd_em_integrate(ctypes.byref(path), ctypes.byref(pot), None, x0, noise,
+                                     x_out, ws, ctypes.c_size_t(ws_bytes), None)
+
+    assert integrate(x0=None) == _lib.PAMD_EINVAL
+    assert integrate(noise=None) == _lib.PAMD_EINVAL
+    assert integrate(x_out=None) == _lib.PAMD_EINVAL
+    # noise (1000 slices of 2592 doubles) starting inside x_out
+    assert integrate(noise=ctypes.c_void_p(0x20000000 + 8 * 2592 * 999)) == _lib.PAMD_EINVAL
+    assert b"overlaps" in lib.pamd_last_error()
+    assert integrate(ws_bytes=need - 1) == _lib.PAMD_EWORKSPACE
+    assert integrate(ws=FAKE_BAD) == _lib.PAMD_EWORKSPACE
