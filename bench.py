@@ -536,7 +536,7 @@ def bench_em(args, w) -> int:
     system at dt_E = dt / 2: one step = one pamd_em_integrate call over 4096
     time steps.  Also times one path-sampling sweep of the paper's Simulation 2
     schedule on the same system and reports the measured counterpart of the
-    speedup chi (Eq. 20): the wall time of the N_shift dt / dt_E Euler steps
+    speedup chi (Eq. 11): the wall time of the N_shift dt / dt_E Euler steps
     that one shifting event advances, over the N_sample sweeps it costs (the
     shift itself is a ring-buffer offset and is not timed)."""
     w_e = dataclasses.replace(w, dt=w.dt / SIM2["dt_ratio"], n_steps=EM_STEPS)
