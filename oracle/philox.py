@@ -16,6 +16,9 @@ Stream layout of the sampler (key = (seed mod 2^32, seed >> 32)), for sweep s:
   trial normal   counter (p mod 2^32, p >> 32, s, 3) for pair p = e >> 1 of the flat
                  element index e = n * n_dof + k; element e takes the cos (e even)
                  or the sin (e odd) output.
+and of the integrator's regeneration after shifting event v:
+  regrowth normal  counter (p mod 2^32, p >> 32, v, 4), p and e as for trial normals
+                   (e indexes the shifted path).
 """
 from __future__ import annotations
 
@@ -30,6 +33,7 @@ MASK = 0xFFFFFFFF
 PURPOSE_LEVEL = 1
 PURPOSE_ACCEPT = 2
 PURPOSE_TRIAL = 3
+PURPOSE_REGROW = 4
 
 
 def philox4x32_10(ctr, key):
@@ -81,14 +85,20 @@ def accept_uniforms(seed: int, sweep: int, n_fragments: int):
     return uniform52(w[0], w[1])
 
 
-def trial_normals(seed: int, sweep: int, n_elements: int, first: int = 0):
+def trial_normals(seed: int, sweep: int, n_elements: int, first: int = 0,
+                  purpose: int = PURPOSE_TRIAL):
     """Standard normals for flat element indices first .. first + n_elements - 1."""
     e = np.arange(first, first + n_elements, dtype=np.uint64)
     p = e >> np.uint64(1)
     w = philox4x32_10((p & np.uint64(MASK), p >> np.uint64(32), np.full_like(p, sweep),
-                       np.full_like(p, PURPOSE_TRIAL)), seed_key(seed))
+                       np.full_like(p, purpose)), seed_key(seed))
     u1 = uniform52(w[0], w[1])
     u2 = uniform52(w[2], w[3])
     rad = np.sqrt(-2.0 * np.log(u1))
     ang = 2.0 * np.pi * u2
     return np.where((e & np.uint64(1)) == 0, rad * np.cos(ang), rad * np.sin(ang))
+
+
+def regrow_normals(seed: int, event: int, n_elements: int, first: int = 0):
+    """Standard normals of the regrowth after shifting event `event`."""
+    return trial_normals(seed, event, n_elements, first, PURPOSE_REGROW)
