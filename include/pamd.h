@@ -269,6 +269,48 @@ int pamd_mh_step(const pamd_path* path, const pamd_potential* pot, const pamd_tu
                  void* ws, size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------------------
+ * Path-based integration (Sec. II B, Figs. 1-2): sample the path, shift it
+ * along itself, regrow it, repeat.
+ *
+ * pamd_shift performs one shifting event (Fig. 2B) with s = n_shift:
+ *     x_out[n] = x_in[n + s]                      n = 0 .. N - s
+ *     x_out[n] = x_out[n - 1] + sqrt(2 D dt) z_n   n = N - s + 1 .. N
+ * (regrowth by free Brownian continuation, the trial distribution of Sec. III),
+ * excess_out[n] = excess_in[n + s] for n < N - s (the last s entries are left
+ * for the caller: pamd_excess_action on the sub-path x_out + (N - s) slices
+ * with n_steps = s gives them), and traj_out (if not NULL) receives
+ * x_in[1 .. s], the slices that join the integrated trajectory.
+ * z_n: Philox4x32-10 with key (seed mod 2^32, seed >> 32), counter
+ * (p mod 2^32, p >> 32, v, 4) with p = e >> 1 for flat element index
+ * e = n * n_dim * n_atoms + k of x_out, Box-Muller as for trial normals, and v
+ * read from *event_counter (device int64), which the call increments.
+ *   x_in, x_out         device paths, must not overlap
+ *   excess_in/out       device, N float64 each, both or neither, must not overlap
+ *   traj_out            device, n_shift * n_dim * n_atoms float64, or NULL
+ *   requires 1 <= n_shift <= N.
+ * ---------------------------------------------------------------------- */
+int pamd_shift(const pamd_path* path, uint64_t seed, int32_t n_shift, int64_t* event_counter,
+               const double* x_in, double* x_out, const double* excess_in, double* excess_out,
+               double* traj_out, void* stream);
+
+/* The integration loop: n_events shifting events, each preceded by n_sample
+ * Monte Carlo steps (pamd_mh_step with levels l_min..l_max), with the
+ * regrown steps' excess evaluated after every shift.  x and excess hold the
+ * path and its excess on entry and on exit; x_alt, excess_alt and trial are
+ * scratch of the same sizes (the path moves between x and x_alt from event
+ * to event).  counters (device int64[2]) = {sweep, event}, both advanced.
+ * traj_out (device, n_events * n_shift slices, or NULL) receives the
+ * integrated trajectory, x_1 .. x_{n_shift} of every event in time order.
+ * Workspace: pamd_run_workspace_size.  Enqueues kernels only. */
+int pamd_run_workspace_size(const pamd_path* path, const pamd_potential* pot,
+                            const pamd_tuning* tuning, int32_t n_shift, size_t* bytes);
+int pamd_run(const pamd_path* path, const pamd_potential* pot, const pamd_tuning* tuning,
+             uint64_t seed, int32_t l_min, int32_t l_max, int32_t n_sample, int32_t n_shift,
+             int32_t n_events, int64_t* counters, double* x, double* x_alt, double* trial,
+             double* excess, double* excess_alt, double* traj_out, void* ws, size_t ws_bytes,
+             void* stream);
+
+/* ------------------------------------------------------------------------
  * Sequential Euler-Maruyama integration (Eq. 2, Sec. II A): the time-stepping
  * baseline that path sampling parallelises.  Steps
  *     x_{n+1} = x_n + (dt / gamma) F(x_n) + sqrt(2 D dt) xi_n,   n = 0..N-1,

@@ -22,7 +22,8 @@ __all__ = [
     "PamdPath", "PamdPotential", "PamdTuning", "PamdError", "make_path", "make_potential",
     "make_tuning", "pamd_workspace_size", "pamd_action", "pamd_action_grad",
     "pamd_excess_action", "pamd_log_norm", "pamd_mh_workspace_size", "pamd_mh_step",
-    "pamd_em_workspace_size", "pamd_em_integrate", "pamd_autotune", "PamdBatch", "PamdGraph", "workspace",
+    "pamd_em_workspace_size", "pamd_em_integrate", "pamd_shift", "pamd_run_workspace_size",
+    "pamd_run", "pamd_autotune", "PamdBatch", "PamdGraph", "workspace",
 ]
 
 
@@ -148,6 +149,39 @@ def pamd_mh_step(path, pot, seed: int, l_min: int, l_max: int, sweep_counter: to
               _ptr(frag_delta, name="frag_delta"), _ptr(frag_accept, torch.int32, "frag_accept"),
               _ptr(step_info, torch.int32, "step_info"), _ptr(ws, None, "ws"),
               ctypes.c_size_t(ws.numel()), _stream(stream))
+
+
+# ---------------------------------------------------------------------------
+# path-based integration: shifting events and the loop
+# ---------------------------------------------------------------------------
+def pamd_shift(path, seed: int, n_shift: int, event_counter: torch.Tensor, x_in, x_out,
+               excess_in=None, excess_out=None, traj_out=None, stream=None):
+    _lib.call("pamd_shift", ctypes.byref(path), ctypes.c_uint64(seed), ctypes.c_int32(n_shift),
+              _ptr(event_counter, torch.int64, "event_counter"), _ptr(x_in, name="x_in"),
+              _ptr(x_out, name="x_out"), _ptr(excess_in, name="excess_in"),
+              _ptr(excess_out, name="excess_out"), _ptr(traj_out, name="traj_out"),
+              _stream(stream))
+
+
+def pamd_run_workspace_size(path, pot, n_shift: int, tuning=None) -> int:
+    n = ctypes.c_size_t(0)
+    _lib.call("pamd_run_workspace_size", ctypes.byref(path), ctypes.byref(pot), _ref(tuning),
+              ctypes.c_int32(n_shift), ctypes.byref(n))
+    return int(n.value)
+
+
+def pamd_run(path, pot, seed: int, l_min: int, l_max: int, n_sample: int, n_shift: int,
+             n_events: int, counters: torch.Tensor, x, x_alt, trial, excess, excess_alt,
+             traj_out=None, ws=None, tuning=None, stream=None):
+    if ws is None:
+        ws = workspace(pamd_run_workspace_size(path, pot, n_shift, tuning))
+    _lib.call("pamd_run", ctypes.byref(path), ctypes.byref(pot), _ref(tuning),
+              ctypes.c_uint64(seed), ctypes.c_int32(l_min), ctypes.c_int32(l_max),
+              ctypes.c_int32(n_sample), ctypes.c_int32(n_shift), ctypes.c_int32(n_events),
+              _ptr(counters, torch.int64, "counters"), _ptr(x, name="x"),
+              _ptr(x_alt, name="x_alt"), _ptr(trial, name="trial"), _ptr(excess, name="excess"),
+              _ptr(excess_alt, name="excess_alt"), _ptr(traj_out, name="traj_out"),
+              _ptr(ws, None, "ws"), ctypes.c_size_t(ws.numel()), _stream(stream))
 
 
 # ---------------------------------------------------------------------------

@@ -641,6 +641,129 @@ int pamd_em_integrate(const pamd_path* p, const pamd_potential* v, const pamd_tu
 }
 
 // ---------------------------------------------------------------------------
+// Path-based integration: shifting events and the sample-shift-regrow loop
+// ---------------------------------------------------------------------------
+}  // extern "C"
+
+namespace {
+bool overlap(const void* a, size_t na, const void* b, size_t nb) {
+  const char *pa = (const char*)a, *pb = (const char*)b;
+  return pa < pb + nb && pb < pa + na;
+}
+
+// The path of steps N - n_shift .. N: the part that a shifting event regrows.
+pamd_path tail_path(const pamd_path* p, int32_t n_shift) {
+  pamd_path q = *p;
+  q.n_steps = n_shift;
+  return q;
+}
+}  // namespace
+
+extern "C" {
+
+int pamd_shift(const pamd_path* p, uint64_t seed, int32_t n_shift, int64_t* event_counter,
+               const double* x_in, double* x_out, const double* excess_in, double* excess_out,
+               double* traj_out, void* stream) {
+  int rc;
+  if ((rc = check_path(p))) return rc;
+  if (n_shift < 1 || n_shift > p->n_steps)
+    return fail(PAMD_EINVAL, "n_shift must be in [1, n_steps] (got %d)", n_shift);
+  if (!event_counter || !x_in || !x_out)
+    return fail(PAMD_EINVAL, "event_counter, x_in and x_out must be non-NULL");
+  if (!excess_in != !excess_out)
+    return fail(PAMD_EINVAL, "excess_in and excess_out must both be given or both be NULL");
+  const int64_t dof = (int64_t)p->n_dim * p->n_atoms;
+  const size_t xb = sizeof(double) * (size_t)(p->n_steps + 1) * dof;
+  const size_t eb = sizeof(double) * (size_t)p->n_steps;
+  if (overlap(x_in, xb, x_out, xb)) return fail(PAMD_EINVAL, "x_in and x_out overlap");
+  if (excess_in && overlap(excess_in, eb, excess_out, eb))
+    return fail(PAMD_EINVAL, "excess_in and excess_out overlap");
+  if (traj_out && overlap(traj_out, sizeof(double) * (size_t)n_shift * dof, x_out, xb))
+    return fail(PAMD_EINVAL, "traj_out overlaps x_out");
+  ShiftArgs a;
+  a.x_in = x_in;
+  a.x_out = x_out;
+  a.ex_in = excess_in;
+  a.ex_out = excess_out;
+  a.traj = traj_out;
+  a.event_counter = event_counter;
+  a.n_steps = p->n_steps;
+  a.n_dof = dof;
+  a.n_shift = n_shift;
+  a.key0 = (uint32_t)(seed & 0xffffffffu);
+  a.key1 = (uint32_t)(seed >> 32);
+  a.sig = std::sqrt(2.0 * p->D * p->dt);
+  PAMD_HIP(launch_shift(a, (hipStream_t)stream));
+  return PAMD_OK;
+}
+
+int pamd_run_workspace_size(const pamd_path* p, const pamd_potential* v, const pamd_tuning* t,
+                            int32_t n_shift, size_t* bytes) {
+  if (!bytes) return fail(PAMD_EINVAL, "bytes is NULL");
+  int rc;
+  if ((rc = check_path(p))) return rc;
+  if (n_shift < 1 || n_shift > p->n_steps)
+    return fail(PAMD_EINVAL, "n_shift must be in [1, n_steps] (got %d)", n_shift);
+  Plan P, Q;
+  if ((rc = make_plan(p, v, t, true, P))) return rc;
+  const pamd_path q = tail_path(p, n_shift);
+  if ((rc = make_plan(&q, v, t, false, Q))) return rc;
+  *bytes = std::max(P.total, Q.total);
+  return PAMD_OK;
+}
+
+int pamd_run(const pamd_path* p, const pamd_potential* v, const pamd_tuning* t, uint64_t seed,
+             int32_t l_min, int32_t l_max, int32_t n_sample, int32_t n_shift, int32_t n_events,
+             int64_t* counters, double* x, double* x_alt, double* trial, double* excess,
+             double* excess_alt, double* traj_out, void* ws, size_t ws_bytes, void* stream) {
+  size_t need = 0;
+  int rc = pamd_run_workspace_size(p, v, t, n_shift, &need);
+  if (rc) return rc;
+  if (n_sample < 0 || n_events < 0)
+    return fail(PAMD_EINVAL, "n_sample and n_events must be >= 0 (got %d, %d)", n_sample, n_events);
+  if (l_min < 1 || l_max < l_min || l_max > 30)
+    return fail(PAMD_EINVAL, "levels must satisfy 1 <= l_min <= l_max <= 30 (got %d, %d)", l_min, l_max);
+  if (((int64_t)1 << l_max) > p->n_steps)
+    return fail(PAMD_EINVAL, "2^l_max = %lld exceeds n_steps = %lld", (long long)1 << l_max, (long long)p->n_steps);
+  if (!counters || !x || !x_alt || !trial || !excess || !excess_alt)
+    return fail(PAMD_EINVAL, "counters, x, x_alt, trial, excess and excess_alt must be non-NULL");
+  const int64_t dof = (int64_t)p->n_dim * p->n_atoms;
+  const size_t xb = sizeof(double) * (size_t)(p->n_steps + 1) * dof;
+  const size_t eb = sizeof(double) * (size_t)p->n_steps;
+  if (overlap(x, xb, x_alt, xb) || overlap(x, xb, trial, xb) || overlap(x_alt, xb, trial, xb))
+    return fail(PAMD_EINVAL, "x, x_alt and trial must not overlap");
+  if (overlap(excess, eb, excess_alt, eb)) return fail(PAMD_EINVAL, "excess and excess_alt overlap");
+  Plan W;
+  W.total = need;
+  if ((rc = check_ws(W, ws, ws_bytes))) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  const pamd_path q = tail_path(p, n_shift);
+  const int64_t keep = p->n_steps - n_shift;
+  double *xc = x, *xo = x_alt, *ec = excess, *eo = excess_alt;
+  for (int32_t e = 0; e < n_events; ++e) {
+    for (int32_t k = 0; k < n_sample; ++k) {
+      rc = pamd_mh_step(p, v, t, seed, l_min, l_max, counters, xc, ec, trial, nullptr, nullptr,
+                        nullptr, ws, ws_bytes, stream);
+      if (rc) return rc;
+    }
+    rc = pamd_shift(p, seed, n_shift, counters + 1, xc, xo, ec, eo,
+                    traj_out ? traj_out + (size_t)e * n_shift * dof : nullptr, stream);
+    if (rc) return rc;
+    // excess of the regrown steps
+    rc = pamd_excess_action(&q, v, t, xo + (size_t)keep * dof, eo + keep, nullptr, ws, ws_bytes,
+                            stream);
+    if (rc) return rc;
+    std::swap(xc, xo);
+    std::swap(ec, eo);
+  }
+  if (xc != x) {
+    PAMD_HIP(launch_copy(xc, x, (int64_t)(p->n_steps + 1) * dof, st));
+    PAMD_HIP(launch_copy(ec, excess, p->n_steps, st));
+  }
+  return PAMD_OK;
+}
+
+// ---------------------------------------------------------------------------
 // Autotuning
 // ---------------------------------------------------------------------------
 int pamd_autotune(const pamd_path* p, const pamd_potential* v, const double* x,

@@ -220,4 +220,21 @@ hipError_t launch_mh_prepare(const MHArgs& m, hipStream_t st);
 hipError_t launch_mh_trial(const MHArgs& m, hipStream_t st);
 hipError_t launch_mh_accept(const MHArgs& m, hipStream_t st);
 
+// Shifting event of the path-based integrator.
+struct ShiftArgs {
+  const double* x_in;
+  double* x_out;
+  const double* ex_in;   // may be null (then ex_out is too)
+  double* ex_out;
+  double* traj;          // may be null
+  int64_t* event_counter;
+  int64_t n_steps;
+  int64_t n_dof;
+  int64_t n_shift;
+  uint32_t key0, key1;
+  double sig;            // sqrt(2 D dt)
+};
+hipError_t launch_shift(const ShiftArgs& a, hipStream_t st);
+hipError_t launch_copy(const double* src, double* dst, int64_t n, hipStream_t st);
+
 }  // namespace pamd

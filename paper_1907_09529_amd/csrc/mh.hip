@@ -47,10 +47,12 @@ __device__ __forceinline__ double uniform52(uint32_t a, uint32_t b) {
   return (k + 0.5) * (1.0 / 4503599627370496.0);
 }
 
-__device__ __forceinline__ double trial_normal(uint64_t e, uint32_t sweep, uint32_t k0,
-                                               uint32_t k1) {
+// Normal variate of flat element e from stream `purpose` (3: trial moves of
+// sweep `ctr`, 4: regrowth after shifting event `ctr`).
+__device__ __forceinline__ double stream_normal(uint64_t e, uint32_t ctr, uint32_t purpose,
+                                                uint32_t k0, uint32_t k1) {
   const uint64_t p = e >> 1;
-  const U4 w = philox((uint32_t)p, (uint32_t)(p >> 32), sweep, 3u, k0, k1);
+  const U4 w = philox((uint32_t)p, (uint32_t)(p >> 32), ctr, purpose, k0, k1);
   const double u1 = uniform52(w.v[0], w.v[1]);
   const double u2 = uniform52(w.v[2], w.v[3]);
   const double rad = sqrt(-2.0 * log(u1));
@@ -106,14 +108,14 @@ __global__ void mh_trial_kernel(MHArgs m) {
     m.trial[a * m.n_dof + e] = y;
     if (nose) {
       for (int64_t k = a; k < b; ++k) {
-        y = fma(m.sig, trial_normal((uint64_t)(k + 1) * m.n_dof + e, s, m.key0, m.key1), y);
+        y = fma(m.sig, stream_normal((uint64_t)(k + 1) * m.n_dof + e, s, 3u, m.key0, m.key1), y);
         m.trial[(k + 1) * m.n_dof + e] = y;
       }
     } else {
       const double xb = m.x[b * m.n_dof + e];
       for (int64_t k = a; k < b - 1; ++k) {
         const double rem = (double)(b - k);
-        const double z = trial_normal((uint64_t)(k + 1) * m.n_dof + e, s, m.key0, m.key1);
+        const double z = stream_normal((uint64_t)(k + 1) * m.n_dof + e, s, 3u, m.key0, m.key1);
         y = y + (xb - y) / rem + m.sig * sqrt((rem - 1.0) / rem) * z;
         m.trial[(k + 1) * m.n_dof + e] = y;
       }
@@ -210,6 +212,66 @@ hipError_t launch_mh_accept(const MHArgs& m, hipStream_t st) {
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(mh_advance_kernel, dim3(1), dim3(64), 0, st, m);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Shifting event of the path-based integrator (Sec. II B, Fig. 2B)
+// ---------------------------------------------------------------------------
+// x_out[n] = x_in[n + s] for n = 0 .. N - s, the kept excess terms move along,
+// and x_in[1 .. s] leave as trajectory.
+__global__ void shift_copy_kernel(ShiftArgs a) {
+  const int64_t keep = a.n_steps - a.n_shift;
+  const int64_t off = (int64_t)a.n_shift * a.n_dof;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (int64_t t = t0; t < (keep + 1) * a.n_dof; t += stride) a.x_out[t] = a.x_in[t + off];
+  if (a.ex_out)
+    for (int64_t n = t0; n < keep; n += stride) a.ex_out[n] = a.ex_in[n + a.n_shift];
+  if (a.traj)
+    for (int64_t t = t0; t < off; t += stride) a.traj[t] = a.x_in[t + a.n_dof];
+}
+
+// Slices N - s + 1 .. N regrown from the new slice N - s (= x_in[N]) by free
+// Brownian continuation, one thread per degree of freedom.
+__global__ void shift_regrow_kernel(ShiftArgs a) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= a.n_dof) return;
+  const uint32_t v = (uint32_t)(*a.event_counter);
+  double y = a.x_in[a.n_steps * a.n_dof + k];
+  for (int64_t n = a.n_steps - a.n_shift + 1; n <= a.n_steps; ++n) {
+    y = fma(a.sig, stream_normal((uint64_t)n * a.n_dof + k, v, 4u, a.key0, a.key1), y);
+    a.x_out[n * a.n_dof + k] = y;
+  }
+}
+
+__global__ void counter_advance_kernel(int64_t* c) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *c += 1;
+}
+
+__global__ void copy_kernel(const double* src, double* dst, int64_t n) {
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n;
+       t += (int64_t)gridDim.x * blockDim.x)
+    dst[t] = src[t];
+}
+
+hipError_t launch_shift(const ShiftArgs& a, hipStream_t st) {
+  const int64_t total = (a.n_steps - a.n_shift + 1) * a.n_dof;
+  const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>((total + 255) / 256, 16384));
+  hipLaunchKernelGGL(shift_copy_kernel, dim3((unsigned)blocks), dim3(256), 0, st, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(shift_regrow_kernel, dim3((unsigned)((a.n_dof + 255) / 256)), dim3(256), 0,
+                     st, a);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(counter_advance_kernel, dim3(1), dim3(64), 0, st, a.event_counter);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy(const double* src, double* dst, int64_t n, hipStream_t st) {
+  const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 16384));
+  hipLaunchKernelGGL(copy_kernel, dim3((unsigned)blocks), dim3(256), 0, st, src, dst, n);
   return hipGetLastError();
 }
 

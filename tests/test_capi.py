@@ -245,3 +245,40 @@ def test_em_validation():
     assert b"overlaps" in lib.pamd_last_error()
     assert integrate(ws_bytes=need - 1) == _lib.PAMD_EWORKSPACE
     assert integrate(ws=FAKE_BAD) == _lib.PAMD_EWORKSPACE
+
+
+def test_shift_and_run_validation():
+    lib = P.load()
+    path = P.make_path(16, 1, 1, 0.4, 1.0, 1.0)
+    pot = P.make_potential("harmonic")
+    A, B = ctypes.c_void_p(0x10000000), ctypes.c_void_p(0x20000000)
+    EA, EB = ctypes.c_void_p(0x30000000), ctypes.c_void_p(0x40000000)
+
+    def shift(n_shift=2, x_in=A, x_out=B, e_in=EA, e_out=EB, counter=FAKE):
+        return lib.pamd_shift(ctypes.byref(path), 1, n_shift, counter, x_in, x_out, e_in, e_out,
+                              None, None)
+
+    for bad in (0, 17):
+        assert shift(n_shift=bad) == _lib.PAMD_EINVAL
+    assert shift(counter=None) == _lib.PAMD_EINVAL
+    assert shift(x_out=ctypes.c_void_p(0x10000000 + 8)) == _lib.PAMD_EINVAL      # overlaps x_in
+    assert shift(e_out=None) == _lib.PAMD_EINVAL                                 # one of two
+    n = ctypes.c_size_t(0)
+    assert lib.pamd_run_workspace_size(ctypes.byref(path), ctypes.byref(pot), None, 2,
+                                       ctypes.byref(n)) == 0 and n.value > 0
+    assert lib.pamd_run_workspace_size(ctypes.byref(path), ctypes.byref(pot), None, 0,
+                                       ctypes.byref(n)) == _lib.PAMD_EINVAL
+
+    def run(l_min=3, l_max=3, n_sample=2, n_shift=2, n_events=1, x_alt=B, ws_bytes=None):
+        need = ctypes.c_size_t(0)
+        lib.pamd_run_workspace_size(ctypes.byref(path), ctypes.byref(pot), None, n_shift,
+                                    ctypes.byref(need))
+        return lib.pamd_run(ctypes.byref(path), ctypes.byref(pot), None, 1, l_min, l_max,
+                            n_sample, n_shift, n_events, FAKE, A, x_alt,
+                            ctypes.c_void_p(0x50000000), EA, EB, None, FAKE,
+                            ctypes.c_size_t(need.value if ws_bytes is None else ws_bytes), None)
+
+    assert run(l_max=5) == _lib.PAMD_EINVAL            # 2^5 > 16 steps
+    assert run(n_sample=-1) == _lib.PAMD_EINVAL
+    assert run(x_alt=A) == _lib.PAMD_EINVAL
+    assert run(ws_bytes=8) == _lib.PAMD_EWORKSPACE
