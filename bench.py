@@ -148,7 +148,8 @@ def _parser():
     ap.add_argument("--variant", choices=["fused", "plain", "fp32_force"], default="fused")
     ap.add_argument("--workload", default="lj864",
                     help="lj864 (default), lj108, lj27, ho1d, batch64, sweep4000, "
-                         "em864 or em27 (sequential Euler-Maruyama integration)")
+                         "em864 or em27 (sequential Euler-Maruyama integration), "
+                         "pamd864 or pamd27 (the path-based integration loop)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--list", choices=["auto", "full", "half"], default="auto")
@@ -195,6 +196,8 @@ def main(argv=None) -> int:
         return bench_sweep(args)
     if args.workload in ("em864", "em27"):
         return bench_em(args, W.workload("lj" + args.workload[2:]))
+    if args.workload in ("pamd864", "pamd27"):
+        return bench_pamd(args, W.workload("lj" + args.workload[4:]))
     w = W.workload(args.workload)
     if w.potential == "harmonic":
         return bench_harmonic(args, w)
@@ -652,6 +655,128 @@ def bench_em(args, w) -> int:
               "parallelism": "single GPU, one workgroup"}
     _line(units / (ms * 1e-3), ms, args, "f64", config, roof, baseline,
           metric="em_slice_atom_steps_per_s", unit="slice_atom_steps/s")
+    return 0
+
+
+def bench_pamd(args, w) -> int:
+    """The path-based integration loop with the paper's Simulation 2 schedule
+    on one Lennard-Jones system: one step = one shifting event (N_sample MC
+    sweeps of the 4096-step path, shift, regrowth, excess of the regrown
+    steps), replayed from a captured graph of two events.  Reports the
+    simulated time advanced per wall-clock second, the same for sequential
+    Euler at dt_E = dt / 2, and their ratio (the measured speedup chi)."""
+    n_path, n_shift = SIM2["n_path"], SIM2["n_shift"]
+    print(f"[bench] {w.name}: path-based integration, {n_path}-step path, shift {n_shift}",
+          file=sys.stderr, flush=True)
+    x0 = W.initial_lattice(w.n_atoms, w.box)
+    baseline = None
+    if not args.no_cpu_baseline:
+        from oracle import action as OA
+        from oracle.potentials import LennardJones
+        pot_o = LennardJones(eps=w.eps, sigma=w.sigma, rc=w.cutoff, box=w.box)
+        xi_o, _ = W.draw_noise(w.with_steps(16))
+        from oracle import em as OE
+        Xo = OE.em_path(x0, xi_o, pot_o, w.dt, w.D, w.gamma)
+        t0 = time.perf_counter()
+        reps = 0
+        while time.perf_counter() - t0 < 10.0:
+            OA.per_step_action(Xo, pot_o, w.dt, w.D, w.gamma)
+            reps += 1
+        per_slice = (time.perf_counter() - t0) / (reps * 16)
+        # one event = N_sample sweeps, each evaluating the trial path's n_path steps
+        ev_s = SIM2["n_sample"] * n_path * per_slice
+        baseline = {"value": n_shift * w.dt / ev_s, "unit": "md_time/s", "cores": 1,
+                    "kind": "oracle",
+                    "sample": f"{reps} evaluations of the oracle's per-step action on a 16-step "
+                              f"path of this system ({per_slice * 1e3:.3f} ms per slice), scaled "
+                              f"to one event's {SIM2['n_sample']} x {n_path} slices; the "
+                              "trial generation and accept step are not counted"}
+
+    import torch
+    import paper_1907_09529_amd as P
+    P.load()
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    pot = P.make_potential("lj", eps=w.eps, sigma=w.sigma, rc=w.cutoff, box=w.box)
+    path = P.make_path(n_path, w.n_atoms, 3, w.dt, w.D, w.gamma, "fp64")
+    x0_d = torch.from_numpy(x0).to(dev)
+    xi = torch.from_numpy(W.draw_noise(w.with_steps(n_path))[0]).to(dev)
+    x = torch.empty((n_path + 1, 3, w.n_atoms), dtype=torch.float64, device=dev)
+    P.pamd_em_integrate(path, pot, x0_d, xi, x, ws=P.workspace(P.pamd_em_workspace_size(path, pot)))
+    del xi
+    x_alt, trial = torch.empty_like(x), torch.empty_like(x)
+    ex = torch.empty(n_path, dtype=torch.float64, device=dev)
+    ex_alt = torch.empty_like(ex)
+    P.pamd_excess_action(path, pot, x, ex)
+    counters = torch.zeros(2, dtype=torch.int64, device=dev)
+    traj = torch.empty((2 * n_shift, 3, w.n_atoms), dtype=torch.float64, device=dev)
+    ws = P.workspace(P.pamd_run_workspace_size(path, pot, n_shift))
+    s = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    g = P.PamdGraph()
+    with torch.cuda.stream(s):
+        g.begin(s)
+        P.pamd_run(path, pot, 0x5EED1907, SIM2["l_min"], SIM2["l_max"], SIM2["n_sample"], n_shift,
+                   2, counters, x, x_alt, trial, ex, ex_alt, traj, ws=ws, stream=s)
+        g.end(s)
+        for _ in range(args.warmup):
+            g.launch(s)
+    s.synchronize()
+    reps = max(1, args.steps // 2)
+    ev = HipEvents()
+    t0 = time.perf_counter()
+    HipEvents.hip.hipEventRecord(ev.a, ctypes.c_void_p(s.cuda_stream))
+    for _ in range(reps):
+        g.launch(s)
+    HipEvents.hip.hipEventRecord(ev.b, ctypes.c_void_p(s.cuda_stream))
+    s.synchronize()
+    t1 = time.perf_counter()
+    ms = (t1 - t0) * 1e3 / (2 * reps)
+    ev_ms = ev.elapsed_ms() / (2 * reps)
+    ev.close()
+    g.close()
+    assert bool(torch.isfinite(x).all())
+    # the excess-mode fused kernel alone on the current path
+    lib = P.load()
+    kev = [HipEvents() for _ in range(3)]
+    for e in kev:
+        lib.pamd_profile_events(e.a, e.b)
+        P.pamd_excess_action(path, pot, x, ex_alt)
+    k_ms = float(np.mean([e.elapsed_ms() for e in kev]))
+    for e in kev:
+        e.close()
+    Xh = x.cpu().numpy()
+    ppa = pairs_per_atom(Xh, w.box, w.cutoff, n_sample=4)
+    flop_unit = ppa * FLOP_FORCE_PAIR + 24       # force pass, residual, excess terms
+    achieved = flop_unit * n_path * w.n_atoms / (k_ms * 1e-3)
+    # sequential Euler on the same system at dt_E = dt / 2
+    w_e = dataclasses.replace(w, dt=w.dt / SIM2["dt_ratio"], n_steps=EM_STEPS)
+    path_e = P.make_path(EM_STEPS, w.n_atoms, 3, w_e.dt, w.D, w.gamma, "fp64")
+    xi_e = torch.from_numpy(W.draw_noise(w_e)[0]).to(dev)
+    out = torch.empty((EM_STEPS + 1, 3, w.n_atoms), dtype=torch.float64, device=dev)
+    ws_e = P.workspace(P.pamd_em_workspace_size(path_e, pot))
+    P.pamd_em_integrate(path_e, pot, x0_d, xi_e, out, ws=ws_e)
+    eev = HipEvents()
+    lib.pamd_profile_events(eev.a, eev.b)
+    P.pamd_em_integrate(path_e, pot, x0_d, xi_e, out, ws=ws_e)
+    em_step_ms = eev.elapsed_ms() / EM_STEPS
+    eev.close()
+    md_rate = n_shift * w.dt / (ms * 1e-3)
+    em_rate = w_e.dt / (em_step_ms * 1e-3)
+    roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64_VALU / 1e12,
+            "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VALU, "traffic": None,
+            "kernel": "lj_fused_kernel (excess action of the trial path)", "kernel_ms": k_ms,
+            "flop_per_slice_atom": flop_unit, "pairs_per_atom": ppa}
+    config = {"workload": f"path-based integration, LJ {w.n_atoms} atoms, rho {w.density}, "
+                          f"rc {w.cutoff:.4g}, N_path {n_path}, levels {SIM2['l_min']}.."
+                          f"{SIM2['l_max']}, N_sample {SIM2['n_sample']}, N_shift {n_shift}, "
+                          f"dt {w.dt:g}, graph-replayed events",
+              "n_atoms": w.n_atoms, "n_path": n_path, "event_ms": ms, "event_gpu_ms": ev_ms,
+              "md_time_per_s": md_rate, "euler_md_time_per_s": em_rate,
+              "euler_step_us": em_step_ms * 1e3, "chi_paper": SIM2["n_shift"] * SIM2["dt_ratio"],
+              "chi_measured": md_rate / em_rate, "parallelism": "single GPU"}
+    _line(md_rate, ms, args, "f64", config, roof, baseline, metric="md_time_per_wall_s",
+          unit="md_time/s")
     return 0
 
 

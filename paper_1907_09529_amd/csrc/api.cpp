@@ -220,11 +220,6 @@ int make_plan(const pamd_path* p, const pamd_potential* v, const pamd_tuning* t_
     P.block = t.block ? t.block
                       : (have_cache && cached.block ? cached.block
                                                     : default_block(N, list == PAMD_LIST_HALF));
-    int tile = t.tile ? t.tile : (have_cache && cached.tile ? cached.tile : 0);
-    if (tile <= 0) tile = (int)std::max<int64_t>(1, std::min<int64_t>(32, P.steps / 256));
-    P.tile = (int)std::min<int64_t>(tile, P.steps);
-    P.n_tiles = (int)((P.steps + P.tile - 1) / P.tile);
-    P.grid = std::min(P.n_tiles, kMaxGrid);
     P.half = list == PAMD_LIST_HALF;  // automatic choice: full lists (repeatable, as fast)
     if (P.half && N > fused_half_slots() * P.block)
       return fail(PAMD_EUNSUPPORTED, "half lists need n_atoms <= %d * block", fused_half_slots());
@@ -237,6 +232,20 @@ int make_plan(const pamd_path* p, const pamd_potential* v, const pamd_tuning* t_
       return fail(PAMD_EUNSUPPORTED, "n_atoms = %d needs %zu bytes of LDS per workgroup (max %zu)", N,
                   fused_lds_bytes(N, 0, false, P.half, P.block), kLdsMax);
     }
+    int tile = t.tile ? t.tile : (have_cache && cached.tile ? cached.tile : 0);
+    if (tile <= 0) {
+      // Enough tiles for every CU to hold as many workgroups as its wave slots
+      // (16 at this kernel's register use) and LDS allow: small systems get
+      // short tiles, since a workgroup walks its tile's steps in sequence.
+      const int waves = (P.block + 63) / 64;
+      const int by_lds = (int)std::max<size_t>(1, kLdsMax / std::max<size_t>(P.lds, 1));
+      const int per_cu = std::max(1, std::min(16 / waves, by_lds));
+      const int64_t slots = 256LL * per_cu;
+      tile = (int)std::max<int64_t>(1, std::min<int64_t>(32, (P.steps + slots - 1) / slots));
+    }
+    P.tile = (int)std::min<int64_t>(tile, P.steps);
+    P.n_tiles = (int)((P.steps + P.tile - 1) / P.tile);
+    P.grid = std::min(P.n_tiles, kMaxGrid);
     P.off_bnd = bump(cur, sizeof(double) * 3 * N * (size_t)std::max(0, P.n_tiles - 1));
     // neighbour list, then the exact list; both with one spare chunk per atom
     // neighbour lists ((kmax + 8) per atom) and exact lists (up to two rows

@@ -47,23 +47,42 @@ __device__ __forceinline__ double uniform52(uint32_t a, uint32_t b) {
   return (k + 0.5) * (1.0 / 4503599627370496.0);
 }
 
-// Normal variate of flat element e from stream `purpose` (3: trial moves of
-// sweep `ctr`, 4: regrowth after shifting event `ctr`).
-__device__ __forceinline__ double stream_normal(uint64_t e, uint32_t ctr, uint32_t purpose,
-                                                uint32_t k0, uint32_t k1) {
-  const uint64_t p = e >> 1;
+// Normal variates of flat elements 2p (cosine output) and 2p + 1 (sine output)
+// from stream `purpose` (3: trial moves of sweep `ctr`, 4: regrowth after
+// shifting event `ctr`).
+__device__ __forceinline__ void stream_normal_pair(uint64_t p, uint32_t ctr, uint32_t purpose,
+                                                   uint32_t k0, uint32_t k1, double& even,
+                                                   double& odd) {
   const U4 w = philox((uint32_t)p, (uint32_t)(p >> 32), ctr, purpose, k0, k1);
   const double u1 = uniform52(w.v[0], w.v[1]);
   const double u2 = uniform52(w.v[2], w.v[3]);
   const double rad = sqrt(-2.0 * log(u1));
   double sn, cs;
   sincos(2.0 * M_PI * u2, &sn, &cs);
-  return rad * ((e & 1) ? sn : cs);
+  even = rad * cs;
+  odd = rad * sn;
 }
 
-__global__ void mh_prepare_kernel(MHArgs m) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// Writes the variates of flat elements lo .. hi - 1 to out[e - lo], one
+// Box-Muller pair per thread.
+__device__ __forceinline__ void fill_normals(double* out, uint64_t lo, uint64_t hi, uint32_t ctr,
+                                             uint32_t purpose, uint32_t k0, uint32_t k1) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t p = (lo >> 1) + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; 2 * p < hi;
+       p += stride) {
+    double a, b;
+    stream_normal_pair(p, ctr, purpose, k0, k1, a, b);
+    if (2 * p >= lo) out[2 * p - lo] = a;
+    if (2 * p + 1 < hi) out[2 * p + 1 - lo] = b;
+  }
+}
+
+// Level and offset of the sweep (into state), and the trial variates of
+// every element, stored in `trial` where the trial kernel consumes them.
+__global__ void mh_normals_kernel(MHArgs m) {
   const uint32_t s = (uint32_t)(*m.sweep_counter);
+  fill_normals(m.trial, 0, (uint64_t)(m.n_steps + 1) * m.n_dof, s, 3u, m.key0, m.key1);
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
   const U4 w = philox(0u, 0u, s, 1u, m.key0, m.key1);
   const int l = m.l_min + (int)(w.v[0] % (uint32_t)(m.l_max - m.l_min + 1));
   const int64_t span = (int64_t)1 << l;
@@ -91,11 +110,13 @@ __device__ __forceinline__ void frag_range(int f, int l, int64_t u, int n_frag, 
   nose = (f == n_frag - 1) && (b == N) && ((N - u) % span != 0);
 }
 
+// One thread per fragment and degree of freedom runs the fragment's trial
+// recurrence; the variate of slice k sits in trial[k] until the thread
+// overwrites it (each slot is read only by the thread that writes it).
 __global__ void mh_trial_kernel(MHArgs m) {
   const int l = m.state[0];
   const int64_t u = m.state[1];
   const int n_frag = m.state[2];
-  const uint32_t s = (uint32_t)(*m.sweep_counter);
   const int64_t total = (int64_t)n_frag * m.n_dof;
   for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
        t += (int64_t)gridDim.x * blockDim.x) {
@@ -108,16 +129,18 @@ __global__ void mh_trial_kernel(MHArgs m) {
     m.trial[a * m.n_dof + e] = y;
     if (nose) {
       for (int64_t k = a; k < b; ++k) {
-        y = fma(m.sig, stream_normal((uint64_t)(k + 1) * m.n_dof + e, s, 3u, m.key0, m.key1), y);
-        m.trial[(k + 1) * m.n_dof + e] = y;
+        double* slot = m.trial + (k + 1) * m.n_dof + e;
+        y = fma(m.sig, *slot, y);
+        *slot = y;
       }
     } else {
       const double xb = m.x[b * m.n_dof + e];
       for (int64_t k = a; k < b - 1; ++k) {
         const double rem = (double)(b - k);
-        const double z = stream_normal((uint64_t)(k + 1) * m.n_dof + e, s, 3u, m.key0, m.key1);
+        double* slot = m.trial + (k + 1) * m.n_dof + e;
+        const double z = *slot;
         y = y + (xb - y) / rem + m.sig * sqrt((rem - 1.0) / rem) * z;
-        m.trial[(k + 1) * m.n_dof + e] = y;
+        *slot = y;
       }
       if (b == m.n_steps) m.trial[b * m.n_dof + e] = xb;
     }
@@ -158,8 +181,9 @@ __global__ void mh_accept_kernel(MHArgs m) {
 }
 
 // Copies accepted fragments into x and their excess actions into `excess`,
-// then advances the sweep counter.
+// and advances the sweep counter (no kernel of this sweep reads it later).
 __global__ void mh_commit_kernel(MHArgs m) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) *m.sweep_counter += 1;
   const int l = m.state[0];
   const int64_t u = m.state[1];
   const int64_t total = (m.n_steps + 1) * m.n_dof;
@@ -185,12 +209,10 @@ __global__ void mh_commit_kernel(MHArgs m) {
   }
 }
 
-__global__ void mh_advance_kernel(MHArgs m) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) *m.sweep_counter += 1;
-}
-
 hipError_t launch_mh_prepare(const MHArgs& m, hipStream_t st) {
-  hipLaunchKernelGGL(mh_prepare_kernel, dim3(1), dim3(64), 0, st, m);
+  const int64_t pairs = ((m.n_steps + 1) * m.n_dof + 1) / 2;
+  const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>((pairs + 255) / 256, 16384));
+  hipLaunchKernelGGL(mh_normals_kernel, dim3((unsigned)blocks), dim3(256), 0, st, m);
   return hipGetLastError();
 }
 
@@ -209,9 +231,6 @@ hipError_t launch_mh_accept(const MHArgs& m, hipStream_t st) {
   const int64_t total = (m.n_steps + 1) * m.n_dof;
   const int64_t blocks = std::min<int64_t>((total + 255) / 256, 16384);
   hipLaunchKernelGGL(mh_commit_kernel, dim3((unsigned)blocks), dim3(256), 0, st, m);
-  e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(mh_advance_kernel, dim3(1), dim3(64), 0, st, m);
   return hipGetLastError();
 }
 
@@ -219,9 +238,13 @@ hipError_t launch_mh_accept(const MHArgs& m, hipStream_t st) {
 // Shifting event of the path-based integrator (Sec. II B, Fig. 2B)
 // ---------------------------------------------------------------------------
 // x_out[n] = x_in[n + s] for n = 0 .. N - s, the kept excess terms move along,
-// and x_in[1 .. s] leave as trajectory.
+// x_in[1 .. s] leave as trajectory, and the regrowth variates are stored in
+// the regrown slices of x_out.
 __global__ void shift_copy_kernel(ShiftArgs a) {
   const int64_t keep = a.n_steps - a.n_shift;
+  fill_normals(a.x_out + (keep + 1) * a.n_dof, (uint64_t)(keep + 1) * a.n_dof,
+               (uint64_t)(a.n_steps + 1) * a.n_dof, (uint32_t)(*a.event_counter), 4u, a.key0,
+               a.key1);
   const int64_t off = (int64_t)a.n_shift * a.n_dof;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -233,20 +256,18 @@ __global__ void shift_copy_kernel(ShiftArgs a) {
 }
 
 // Slices N - s + 1 .. N regrown from the new slice N - s (= x_in[N]) by free
-// Brownian continuation, one thread per degree of freedom.
+// Brownian continuation over the stored variates, one thread per degree of
+// freedom; then the event counter advances (the copy kernel has read it).
 __global__ void shift_regrow_kernel(ShiftArgs a) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k == 0) *a.event_counter += 1;
   if (k >= a.n_dof) return;
-  const uint32_t v = (uint32_t)(*a.event_counter);
   double y = a.x_in[a.n_steps * a.n_dof + k];
   for (int64_t n = a.n_steps - a.n_shift + 1; n <= a.n_steps; ++n) {
-    y = fma(a.sig, stream_normal((uint64_t)n * a.n_dof + k, v, 4u, a.key0, a.key1), y);
-    a.x_out[n * a.n_dof + k] = y;
+    double* slot = a.x_out + n * a.n_dof + k;
+    y = fma(a.sig, *slot, y);
+    *slot = y;
   }
-}
-
-__global__ void counter_advance_kernel(int64_t* c) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) *c += 1;
 }
 
 __global__ void copy_kernel(const double* src, double* dst, int64_t n) {
@@ -263,9 +284,6 @@ hipError_t launch_shift(const ShiftArgs& a, hipStream_t st) {
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(shift_regrow_kernel, dim3((unsigned)((a.n_dof + 255) / 256)), dim3(256), 0,
                      st, a);
-  e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(counter_advance_kernel, dim3(1), dim3(64), 0, st, a.event_counter);
   return hipGetLastError();
 }
 
