@@ -709,6 +709,7 @@ def bench_pamd(args, w) -> int:
     ex_alt = torch.empty_like(ex)
     P.pamd_excess_action(path, pot, x, ex)
     counters = torch.zeros(2, dtype=torch.int64, device=dev)
+    stats = torch.zeros(62, dtype=torch.int64, device=dev)
     traj = torch.empty((2 * n_shift, 3, w.n_atoms), dtype=torch.float64, device=dev)
     ws = P.workspace(P.pamd_run_workspace_size(path, pot, n_shift))
     s = torch.cuda.Stream()
@@ -717,7 +718,8 @@ def bench_pamd(args, w) -> int:
     with torch.cuda.stream(s):
         g.begin(s)
         P.pamd_run(path, pot, 0x5EED1907, SIM2["l_min"], SIM2["l_max"], SIM2["n_sample"], n_shift,
-                   2, counters, x, x_alt, trial, ex, ex_alt, traj, ws=ws, stream=s)
+                   2, counters, x, x_alt, trial, ex, ex_alt, traj, level_stats=stats, ws=ws,
+                   stream=s)
         g.end(s)
         for _ in range(args.warmup):
             g.launch(s)
@@ -775,6 +777,9 @@ def bench_pamd(args, w) -> int:
               "md_time_per_s": md_rate, "euler_md_time_per_s": em_rate,
               "euler_step_us": em_step_ms * 1e3, "chi_paper": SIM2["n_shift"] * SIM2["dt_ratio"],
               "chi_measured": md_rate / em_rate, "parallelism": "single GPU"}
+    st = stats.cpu().numpy().reshape(31, 2)
+    config["acceptance_by_level"] = {str(l): round(float(st[l, 1]) / float(st[l, 0]), 4)
+                                     for l in range(31) if st[l, 0] > 0}
     _line(md_rate, ms, args, "f64", config, roof, baseline, metric="md_time_per_wall_s",
           unit="md_time/s")
     return 0

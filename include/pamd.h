@@ -301,14 +301,16 @@ int pamd_shift(const pamd_path* path, uint64_t seed, int32_t n_shift, int64_t* e
  * to event).  counters (device int64[2]) = {sweep, event}, both advanced.
  * traj_out (device, n_events * n_shift slices, or NULL) receives the
  * integrated trajectory, x_1 .. x_{n_shift} of every event in time order.
+ * level_stats (device uint64[62], or NULL) accumulates, for each level l,
+ * the fragments proposed ([2 l]) and accepted ([2 l + 1]); the caller clears it.
  * Workspace: pamd_run_workspace_size.  Enqueues kernels only. */
 int pamd_run_workspace_size(const pamd_path* path, const pamd_potential* pot,
                             const pamd_tuning* tuning, int32_t n_shift, size_t* bytes);
 int pamd_run(const pamd_path* path, const pamd_potential* pot, const pamd_tuning* tuning,
              uint64_t seed, int32_t l_min, int32_t l_max, int32_t n_sample, int32_t n_shift,
              int32_t n_events, int64_t* counters, double* x, double* x_alt, double* trial,
-             double* excess, double* excess_alt, double* traj_out, void* ws, size_t ws_bytes,
-             void* stream);
+             double* excess, double* excess_alt, double* traj_out, uint64_t* level_stats,
+             void* ws, size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------------------
  * Sequential Euler-Maruyama integration (Eq. 2, Sec. II A): the time-stepping

@@ -51,17 +51,24 @@ def regrowth_normals(seed: int, event: int, shape, n_shift: int):
 
 
 def run(X, pot, dt, D, gamma, seed: int, l_min: int, l_max: int, n_sample: int, n_shift: int,
-        n_events: int, sweep0: int = 0, event0: int = 0, method: str = "brute"):
+        n_events: int, sweep0: int = 0, event0: int = 0, method: str = "brute",
+        level_stats=None):
     """n_events shifting events from path X; returns (trajectory, final path).
 
     The trajectory holds x_1 .. x_{N_shift} of every event, in time order
     (n_events * n_shift slices); sweeps and events number from sweep0, event0.
+    level_stats, if given (an integer array of 2 * 31), accumulates the
+    fragments proposed ([2 l]) and accepted ([2 l + 1]) at each level l.
     """
     traj = []
     sweep = sweep0
     for v in range(n_events):
         for _ in range(n_sample):
-            X = _s.mh_step(X, pot, dt, D, gamma, seed, sweep, l_min, l_max, method)["path"]
+            r = _s.mh_step(X, pot, dt, D, gamma, seed, sweep, l_min, l_max, method)
+            X = r["path"]
+            if level_stats is not None:
+                level_stats[2 * r["level"]] += len(r["accepted"])
+                level_stats[2 * r["level"] + 1] += int(np.sum(r["accepted"]))
             sweep += 1
         traj.append(X[1:n_shift + 1].copy())
         X = shift_path(X, n_shift, regrowth_normals(seed, event0 + v, X.shape, n_shift), D, dt)

@@ -88,7 +88,7 @@ _SIGNATURES = {
     "pamd_run_workspace_size": (c_int32, [_PATH, _POT, _TUNE, c_int32, POINTER(c_size_t)]),
     "pamd_run": (c_int32, [_PATH, _POT, _TUNE, c_uint64, c_int32, c_int32, c_int32, c_int32,
                            c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
-                           c_void_p, c_void_p, c_size_t, c_void_p]),
+                           c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
     "pamd_em_workspace_size": (c_int32, [_PATH, _POT, _TUNE, POINTER(c_size_t)]),
     "pamd_em_integrate": (c_int32, [_PATH, _POT, _TUNE, c_void_p, c_void_p, c_void_p, c_void_p,
                                     c_size_t, c_void_p]),

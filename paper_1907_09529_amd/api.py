@@ -172,7 +172,7 @@ def pamd_run_workspace_size(path, pot, n_shift: int, tuning=None) -> int:
 
 def pamd_run(path, pot, seed: int, l_min: int, l_max: int, n_sample: int, n_shift: int,
              n_events: int, counters: torch.Tensor, x, x_alt, trial, excess, excess_alt,
-             traj_out=None, ws=None, tuning=None, stream=None):
+             traj_out=None, level_stats=None, ws=None, tuning=None, stream=None):
     if ws is None:
         ws = workspace(pamd_run_workspace_size(path, pot, n_shift, tuning))
     _lib.call("pamd_run", ctypes.byref(path), ctypes.byref(pot), _ref(tuning),
@@ -181,7 +181,8 @@ def pamd_run(path, pot, seed: int, l_min: int, l_max: int, n_sample: int, n_shif
               _ptr(counters, torch.int64, "counters"), _ptr(x, name="x"),
               _ptr(x_alt, name="x_alt"), _ptr(trial, name="trial"), _ptr(excess, name="excess"),
               _ptr(excess_alt, name="excess_alt"), _ptr(traj_out, name="traj_out"),
-              _ptr(ws, None, "ws"), ctypes.c_size_t(ws.numel()), _stream(stream))
+              _ptr(level_stats, torch.int64, "level_stats"), _ptr(ws, None, "ws"),
+              ctypes.c_size_t(ws.numel()), _stream(stream))
 
 
 # ---------------------------------------------------------------------------

@@ -541,11 +541,14 @@ int pamd_mh_workspace_size(const pamd_path* p, const pamd_potential* v, const pa
   return PAMD_OK;
 }
 
-int pamd_mh_step(const pamd_path* p, const pamd_potential* v, const pamd_tuning* t,
+}  // extern "C"
+
+namespace {
+int mh_step_impl(const pamd_path* p, const pamd_potential* v, const pamd_tuning* t,
                  uint64_t seed, int32_t l_min, int32_t l_max, int64_t* sweep_counter,
                  double* x, double* excess, double* trial, double* frag_delta,
-                 int32_t* frag_accept, int32_t* step_info, void* ws, size_t ws_bytes,
-                 void* stream) {
+                 int32_t* frag_accept, int32_t* step_info, uint64_t* level_stats, void* ws,
+                 size_t ws_bytes, void* stream) {
   Plan P;
   int rc = make_plan(p, v, t, true, P);
   if (rc) return rc;
@@ -568,6 +571,7 @@ int pamd_mh_step(const pamd_path* p, const pamd_potential* v, const pamd_tuning*
   m.state = at<int32_t>(ws, P.off_mh_state);
   m.acc_ws = at<int32_t>(ws, P.off_mh_acc);
   m.sweep_counter = sweep_counter;
+  m.level_stats = reinterpret_cast<unsigned long long*>(level_stats);
   m.n_steps = p->n_steps;
   m.n_dof = P.dof;
   m.key0 = (uint32_t)(seed & 0xffffffffu);
@@ -582,6 +586,18 @@ int pamd_mh_step(const pamd_path* p, const pamd_potential* v, const pamd_tuning*
   if (rc) return rc;
   PAMD_HIP(launch_mh_accept(m, st));
   return PAMD_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int pamd_mh_step(const pamd_path* p, const pamd_potential* v, const pamd_tuning* t,
+                 uint64_t seed, int32_t l_min, int32_t l_max, int64_t* sweep_counter,
+                 double* x, double* excess, double* trial, double* frag_delta,
+                 int32_t* frag_accept, int32_t* step_info, void* ws, size_t ws_bytes,
+                 void* stream) {
+  return mh_step_impl(p, v, t, seed, l_min, l_max, sweep_counter, x, excess, trial, frag_delta,
+                      frag_accept, step_info, nullptr, ws, ws_bytes, stream);
 }
 
 // ---------------------------------------------------------------------------
@@ -724,7 +740,8 @@ int pamd_run_workspace_size(const pamd_path* p, const pamd_potential* v, const p
 int pamd_run(const pamd_path* p, const pamd_potential* v, const pamd_tuning* t, uint64_t seed,
              int32_t l_min, int32_t l_max, int32_t n_sample, int32_t n_shift, int32_t n_events,
              int64_t* counters, double* x, double* x_alt, double* trial, double* excess,
-             double* excess_alt, double* traj_out, void* ws, size_t ws_bytes, void* stream) {
+             double* excess_alt, double* traj_out, uint64_t* level_stats, void* ws,
+             size_t ws_bytes, void* stream) {
   size_t need = 0;
   int rc = pamd_run_workspace_size(p, v, t, n_shift, &need);
   if (rc) return rc;
@@ -751,8 +768,8 @@ int pamd_run(const pamd_path* p, const pamd_potential* v, const pamd_tuning* t, 
   double *xc = x, *xo = x_alt, *ec = excess, *eo = excess_alt;
   for (int32_t e = 0; e < n_events; ++e) {
     for (int32_t k = 0; k < n_sample; ++k) {
-      rc = pamd_mh_step(p, v, t, seed, l_min, l_max, counters, xc, ec, trial, nullptr, nullptr,
-                        nullptr, ws, ws_bytes, stream);
+      rc = mh_step_impl(p, v, t, seed, l_min, l_max, counters, xc, ec, trial, nullptr, nullptr,
+                        nullptr, level_stats, ws, ws_bytes, stream);
       if (rc) return rc;
     }
     rc = pamd_shift(p, seed, n_shift, counters + 1, xc, xo, ec, eo,

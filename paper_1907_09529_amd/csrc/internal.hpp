@@ -210,6 +210,7 @@ struct MHArgs {
   int32_t* state;        // workspace: {l, u, n_frag, n_acc}
   int32_t* acc_ws;       // workspace: accept flag per fragment
   int64_t* sweep_counter;
+  unsigned long long* level_stats;  // may be null: {proposed, accepted} fragments per level, summed
   int64_t n_steps;
   int64_t n_dof;
   uint32_t key0, key1;

@@ -177,6 +177,10 @@ __global__ void mh_accept_kernel(MHArgs m) {
       m.step_info[2] = n_frag;
       m.step_info[3] = (int)tot;
     }
+    if (m.level_stats) {
+      atomicAdd(m.level_stats + 2 * l, (unsigned long long)n_frag);
+      atomicAdd(m.level_stats + 2 * l + 1, (unsigned long long)tot);
+    }
   }
 }
 

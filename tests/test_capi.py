@@ -275,7 +275,7 @@ def test_shift_and_run_validation():
                                     ctypes.byref(need))
         return lib.pamd_run(ctypes.byref(path), ctypes.byref(pot), None, 1, l_min, l_max,
                             n_sample, n_shift, n_events, FAKE, A, x_alt,
-                            ctypes.c_void_p(0x50000000), EA, EB, None, FAKE,
+                            ctypes.c_void_p(0x50000000), EA, EB, None, None, FAKE,
                             ctypes.c_size_t(need.value if ws_bytes is None else ws_bytes), None)
 
     assert run(l_max=5) == _lib.PAMD_EINVAL            # 2^5 > 16 steps

@@ -57,7 +57,7 @@ def test_shift_matches_oracle(device):
     assert int(counter.item()) == 10
 
 
-def run_gpu(w, X, seed, l_min, l_max, n_sample, n_shift, n_events):
+def run_gpu(w, X, seed, l_min, l_max, n_sample, n_shift, n_events, stats=None):
     path, pot = lib_descriptors(w)
     x = dev(X)
     ex = torch.empty(w.n_steps, dtype=torch.float64, device="cuda")
@@ -65,7 +65,8 @@ def run_gpu(w, X, seed, l_min, l_max, n_sample, n_shift, n_events):
     counters = torch.zeros(2, dtype=torch.int64, device="cuda")
     traj = torch.empty((n_events * n_shift,) + X.shape[1:], dtype=torch.float64, device="cuda")
     P.pamd_run(path, pot, seed, l_min, l_max, n_sample, n_shift, n_events, counters, x,
-               torch.empty_like(x), torch.empty_like(x), ex, torch.empty_like(ex), traj)
+               torch.empty_like(x), torch.empty_like(x), ex, torch.empty_like(ex), traj,
+               level_stats=stats)
     torch.cuda.synchronize()
     return traj.cpu().numpy(), x, ex, counters.cpu().numpy()
 
@@ -101,11 +102,72 @@ def test_run_matches_oracle_lj27(device):
     x0 = W.initial_lattice(w.n_atoms, w.box)
     xi, _ = W.draw_noise(w)
     X = OE.em_path(x0, xi, oracle_pot(w), w.dt, w.D, w.gamma)
-    T, x, ex, _ = run_gpu(w, X, 5, 2, 4, 1, 4, 6)
-    T_ref, X_ref = OP.run(X, oracle_pot(w), w.dt, w.D, w.gamma, 5, 2, 4, 1, 4, 6)
+    stats = torch.zeros(62, dtype=torch.int64, device="cuda")
+    T, x, ex, _ = run_gpu(w, X, 5, 2, 4, 1, 4, 6, stats)
+    ref_stats = np.zeros(62, dtype=np.int64)
+    T_ref, X_ref = OP.run(X, oracle_pot(w), w.dt, w.D, w.gamma, 5, 2, 4, 1, 4, 6,
+                          level_stats=ref_stats)
     assert np.max(np.abs(T - T_ref)) <= 1e-10 * w.box
     assert np.max(np.abs(x.cpu().numpy() - X_ref)) <= 1e-10 * w.box
+    assert np.array_equal(stats.cpu().numpy(), ref_stats)      # same fragments, same decisions
     check_final_excess(w, x, ex)
+
+
+def test_level_stats_free_particle(device):
+    """V = 0: every proposed fragment is accepted; levels outside l_min..l_max
+    see none; the counts match the oracle's fragmentations exactly."""
+    w = dataclasses.replace(W.workload("ho1d"), n_steps=64, n_atoms=8, k=0.0, dt=0.05)
+    X = np.cumsum(np.random.default_rng(2).standard_normal((65, 1, 8)) * math.sqrt(0.1), axis=0)
+    stats = torch.zeros(62, dtype=torch.int64, device="cuda")
+    run_gpu(w, X, 17, 2, 5, 3, 8, 10, stats)
+    st = stats.cpu().numpy().reshape(31, 2)
+    assert np.array_equal(st[:, 0], st[:, 1])
+    assert st[2:6, 0].sum() == st[:, 0].sum() > 0
+    ref = np.zeros(62, dtype=np.int64)
+    OP.run(X, oracle_pot(w), w.dt, w.D, w.gamma, 17, 2, 5, 3, 8, 10, level_stats=ref)
+    assert np.array_equal(stats.cpu().numpy(), ref)
+
+
+def test_run_graph_replays_match_eager(device):
+    """A captured two-event run replayed three times, with eager runs on a
+    second set of buffers in between, matches them bit for bit each time."""
+    w = W.workload("lj27").with_steps(64)
+    x0 = W.initial_lattice(w.n_atoms, w.box)
+    xi, _ = W.draw_noise(w)
+    X = OE.em_path(x0, xi, oracle_pot(w), w.dt, w.D, w.gamma)
+    path, pot = lib_descriptors(w)
+
+    def buffers():
+        x = dev(X)
+        ex = torch.empty(w.n_steps, dtype=torch.float64, device="cuda")
+        P.pamd_excess_action(path, pot, x, ex)
+        return dict(counters=torch.zeros(2, dtype=torch.int64, device="cuda"), x=x,
+                    x_alt=torch.empty_like(x), trial=torch.empty_like(x), excess=ex,
+                    excess_alt=torch.empty_like(ex),
+                    traj_out=torch.empty((8,) + X.shape[1:], dtype=torch.float64, device="cuda"),
+                    level_stats=torch.zeros(62, dtype=torch.int64, device="cuda"))
+
+    g_buf, e_buf = buffers(), buffers()
+    ws = P.workspace(P.pamd_run_workspace_size(path, pot, 4))
+    ws_e = P.workspace(P.pamd_run_workspace_size(path, pot, 4))
+    s = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    g = P.PamdGraph()
+    with torch.cuda.stream(s):
+        g.begin(s)
+        P.pamd_run(path, pot, 9, 2, 4, 1, 4, 2, ws=ws, stream=s, **g_buf)
+        g.end(s)
+    try:
+        for rep in range(3):
+            with torch.cuda.stream(s):
+                g.launch(s)
+            s.synchronize()
+            P.pamd_run(path, pot, 9, 2, 4, 1, 4, 2, ws=ws_e, **e_buf)
+            torch.cuda.synchronize()
+            for k in ("x", "excess", "traj_out", "counters", "level_stats"):
+                assert torch.equal(g_buf[k], e_buf[k]), (rep, k)
+    finally:
+        g.close()
 
 
 def test_run_harmonic_follows_the_euler_law(device):
