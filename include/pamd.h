@@ -286,7 +286,8 @@ int pamd_mh_step(const pamd_path* path, const pamd_potential* pot, const pamd_tu
  * read from *event_counter (device int64), which the call increments.
  *   x_in, x_out         device paths, must not overlap
  *   excess_in/out       device, N float64 each, both or neither, must not overlap
- *   traj_out            device, n_shift * n_dim * n_atoms float64, or NULL
+ *   traj_out            device, n_shift * n_dim * n_atoms float64, or NULL; must not
+ *                       overlap x_in or x_out
  *   requires 1 <= n_shift <= N.
  * ---------------------------------------------------------------------- */
 int pamd_shift(const pamd_path* path, uint64_t seed, int32_t n_shift, int64_t* event_counter,

@@ -703,8 +703,9 @@ int pamd_shift(const pamd_path* p, uint64_t seed, int32_t n_shift, int64_t* even
   if (overlap(x_in, xb, x_out, xb)) return fail(PAMD_EINVAL, "x_in and x_out overlap");
   if (excess_in && overlap(excess_in, eb, excess_out, eb))
     return fail(PAMD_EINVAL, "excess_in and excess_out overlap");
-  if (traj_out && overlap(traj_out, sizeof(double) * (size_t)n_shift * dof, x_out, xb))
-    return fail(PAMD_EINVAL, "traj_out overlaps x_out");
+  if (traj_out && (overlap(traj_out, sizeof(double) * (size_t)n_shift * dof, x_out, xb) ||
+                   overlap(traj_out, sizeof(double) * (size_t)n_shift * dof, x_in, xb)))
+    return fail(PAMD_EINVAL, "traj_out overlaps x_in or x_out");
   ShiftArgs a;
   a.x_in = x_in;
   a.x_out = x_out;
