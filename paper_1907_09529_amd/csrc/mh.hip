@@ -113,6 +113,8 @@ __device__ __forceinline__ void frag_range(int f, int l, int64_t u, int n_frag, 
 // One thread per fragment and degree of freedom runs the fragment's trial
 // recurrence; the variate of slice k sits in trial[k] until the thread
 // overwrites it (each slot is read only by the thread that writes it).
+constexpr int RUN = 8;  // variates loaded per batch by the serial recurrences
+
 __global__ void mh_trial_kernel(MHArgs m) {
   const int l = m.state[0];
   const int64_t u = m.state[1];
@@ -127,20 +129,36 @@ __global__ void mh_trial_kernel(MHArgs m) {
     frag_range(f, l, u, n_frag, m.n_steps, a, b, nose);
     double y = m.x[a * m.n_dof + e];
     m.trial[a * m.n_dof + e] = y;
+    // the variates are read RUN at a time ahead of the serial recurrence, so
+    // that their loads overlap
+    double* col = m.trial + e;
     if (nose) {
-      for (int64_t k = a; k < b; ++k) {
-        double* slot = m.trial + (k + 1) * m.n_dof + e;
-        y = fma(m.sig, *slot, y);
-        *slot = y;
+      for (int64_t k0 = a; k0 < b; k0 += RUN) {
+        double z[RUN];
+#pragma unroll
+        for (int j = 0; j < RUN; ++j)
+          if (k0 + j < b) z[j] = col[(k0 + j + 1) * m.n_dof];
+#pragma unroll
+        for (int j = 0; j < RUN; ++j)
+          if (k0 + j < b) {
+            y = fma(m.sig, z[j], y);
+            col[(k0 + j + 1) * m.n_dof] = y;
+          }
       }
     } else {
       const double xb = m.x[b * m.n_dof + e];
-      for (int64_t k = a; k < b - 1; ++k) {
-        const double rem = (double)(b - k);
-        double* slot = m.trial + (k + 1) * m.n_dof + e;
-        const double z = *slot;
-        y = y + (xb - y) / rem + m.sig * sqrt((rem - 1.0) / rem) * z;
-        *slot = y;
+      for (int64_t k0 = a; k0 < b - 1; k0 += RUN) {
+        double z[RUN];
+#pragma unroll
+        for (int j = 0; j < RUN; ++j)
+          if (k0 + j < b - 1) z[j] = col[(k0 + j + 1) * m.n_dof];
+#pragma unroll
+        for (int j = 0; j < RUN; ++j)
+          if (k0 + j < b - 1) {
+            const double rem = (double)(b - (k0 + j));
+            y = y + (xb - y) / rem + m.sig * sqrt((rem - 1.0) / rem) * z[j];
+            col[(k0 + j + 1) * m.n_dof] = y;
+          }
       }
       if (b == m.n_steps) m.trial[b * m.n_dof + e] = xb;
     }
@@ -267,10 +285,18 @@ __global__ void shift_regrow_kernel(ShiftArgs a) {
   if (k == 0) *a.event_counter += 1;
   if (k >= a.n_dof) return;
   double y = a.x_in[a.n_steps * a.n_dof + k];
-  for (int64_t n = a.n_steps - a.n_shift + 1; n <= a.n_steps; ++n) {
-    double* slot = a.x_out + n * a.n_dof + k;
-    y = fma(a.sig, *slot, y);
-    *slot = y;
+  double* col = a.x_out + k;
+  for (int64_t n0 = a.n_steps - a.n_shift + 1; n0 <= a.n_steps; n0 += RUN) {
+    double z[RUN];
+#pragma unroll
+    for (int j = 0; j < RUN; ++j)
+      if (n0 + j <= a.n_steps) z[j] = col[(n0 + j) * a.n_dof];
+#pragma unroll
+    for (int j = 0; j < RUN; ++j)
+      if (n0 + j <= a.n_steps) {
+        y = fma(a.sig, z[j], y);
+        col[(n0 + j) * a.n_dof] = y;
+      }
   }
 }
 
