@@ -767,7 +767,7 @@ def bench_pamd(args, w) -> int:
     em_rate = w_e.dt / (em_step_ms * 1e-3)
     roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64_VALU / 1e12,
             "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VALU, "traffic": None,
-            "kernel": "lj_fused_kernel (excess action of the trial path)", "kernel_ms": k_ms,
+            "kernel": "lj_action_kernel (excess action of the trial path)", "kernel_ms": k_ms,
             "flop_per_slice_atom": flop_unit, "pairs_per_atom": ppa}
     config = {"workload": f"path-based integration, LJ {w.n_atoms} atoms, rho {w.density}, "
                           f"rc {w.cutoff:.4g}, N_path {n_path}, levels {SIM2['l_min']}.."

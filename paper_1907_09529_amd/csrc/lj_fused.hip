@@ -764,7 +764,9 @@ __device__ __forceinline__ void pass2_part(const PathArgs& a, const TileLDS& L, 
                               [&](int t, bool valid) { body(t, valid, std::true_type{}); });
 }
 
-template <bool F32, bool RLDS, bool HALF>
+// GRAD = false compiles the action-only form: no Hessian-vector pass and no
+// exact-list recording (the mode's gradient bit is then ignored).
+template <bool F32, bool RLDS, bool HALF, bool GRAD = true>
 __device__ __forceinline__ void tile_body(const PathArgs& a, int tile, const TileScratch& ts,
                                           char* lds_base) {
   constexpr int XS = RLDS ? XS_R : 3;  // LDS doubles per slot
@@ -775,7 +777,7 @@ __device__ __forceinline__ void tile_body(const PathArgs& a, int tile, const Til
   const int64_t n0 = (int64_t)tile * a.tile;
   const int64_t n1 = min(n0 + (int64_t)a.tile, a.n_steps);
   const size_t slice = (size_t)3 * N;
-  const bool grad = (a.mode & MODE_GRAD) != 0;
+  const bool grad = GRAD && (a.mode & MODE_GRAD) != 0;
   const bool excess = (a.mode & MODE_EXCESS) != 0;
   const int B = blockDim.x;
   const int lane = threadIdx.x & (WAVE - 1);
@@ -905,7 +907,8 @@ __device__ __forceinline__ void tile_body(const PathArgs& a, int tile, const Til
         const bool live = s < N;
         double f[3] = {0.0, 0.0, 0.0};
         if (live)
-          pass1_part<XS, F32, false, 2>(a, L, ts, s, part, 2 * s + part, 2 * N, f[0], f[1], f[2]);
+          pass1_part<XS, F32, false, 2, GRAD>(a, L, ts, s, part, 2 * s + part, 2 * N, f[0], f[1],
+                                              f[2]);
 #pragma unroll
         for (int c = 0; c < 3; ++c) f[c] += __shfl_xor(f[c], 32, WAVE);
         if (live && part == 0) residual(s, f);
@@ -913,7 +916,7 @@ __device__ __forceinline__ void tile_body(const PathArgs& a, int tile, const Til
     } else {
       for (int s = threadIdx.x; s < N; s += B) {
         double f[3];
-        pass1_part<XS, F32, true, 1>(a, L, ts, s, 0, s, N, f[0], f[1], f[2]);
+        pass1_part<XS, F32, true, 1, GRAD>(a, L, ts, s, 0, s, N, f[0], f[1], f[2]);
         // own partial force waits in rho until every partner share has arrived
 #pragma unroll
         for (int c = 0; c < 3; ++c) rho_set(s, c, f[c]);
@@ -1061,6 +1064,15 @@ __global__ void __launch_bounds__(1024) lj_fused_kernel(PathArgs a, BlockScratch
   const TileScratch ts = block_scratch(s);
   for (int t = blockIdx.x; t < a.n_tiles; t += gridDim.x)
     tile_body<F32, RLDS, HALF>(a, t, ts, lds);
+}
+
+// Action (and excess) without the gradient.
+template <bool F32, bool RLDS, bool HALF>
+__global__ void __launch_bounds__(1024) lj_action_kernel(PathArgs a, BlockScratch s) {
+  extern __shared__ __align__(16) char lds[];
+  const TileScratch ts = block_scratch(s);
+  for (int t = blockIdx.x; t < a.n_tiles; t += gridDim.x)
+    tile_body<F32, RLDS, HALF, false>(a, t, ts, lds);
 }
 
 __device__ __forceinline__ PathArgs member_args(const BatchMember& m, const BatchBase& b) {
@@ -1258,7 +1270,8 @@ hipError_t launch_lj_em(const PathArgs& a, const double* xi, double amp, double*
 template <bool F32, bool RLDS, bool HALF>
 static hipError_t launch_fused_t(const PathArgs& a, const BlockScratch& s, const FusedLaunch& L,
                                  hipStream_t st) {
-  auto kern = lj_fused_kernel<F32, RLDS, HALF>;
+  auto kern = (a.mode & MODE_GRAD) ? lj_fused_kernel<F32, RLDS, HALF>
+                                   : lj_action_kernel<F32, RLDS, HALF>;
   hipError_t e = hipFuncSetAttribute((const void*)kern,
                                      hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)L.lds_bytes);
