@@ -296,3 +296,42 @@ def test_sweep4000_full_size_sampled(device):
     picks = {0, tile - 1, tile, w.n_steps - 1, w.n_steps}
     picks |= set(int(v) for v in rng.integers(0, w.n_steps + 1, size=3))
     _check_sampled(w, X, S, s, g, sorted(picks))
+
+
+@pytest.mark.parametrize("variant", ["default", "half", "skin", "ragged_tile", "fp32", "n4000"])
+def test_action_kernel_matches_gradient_kernel(device, variant):
+    """The action-only kernel (pamd_action, pamd_excess_action) runs the same
+    force pass as the gradient kernel without recording exact lists: its
+    per-step terms equal the gradient call's bit for bit with full lists, and
+    to rounding with half lists (whose LDS atomics add in arrival order)."""
+    name, steps, tuning, precision = "lj108", 256, None, "fp64"
+    if variant == "half":
+        tuning = P.make_tuning("fused", block=448, neighbour_list="half")
+    elif variant == "skin":
+        tuning = P.make_tuning("fused", skin=0.05, tile=16)     # rebuilds inside tiles
+    elif variant == "ragged_tile":
+        tuning = P.make_tuning("fused", tile=7)
+    elif variant == "fp32":
+        precision = "fp32_force"
+    elif variant == "n4000":
+        name, steps = "sweep4000", 40
+    w = W.workload(name).with_steps(steps)
+    X = W.tethered_path(w)
+    path, pot = lib_descriptors(w, precision)
+    x = torch.from_numpy(np.ascontiguousarray(X)).cuda()
+    ps_a = torch.empty(w.n_steps, dtype=torch.float64, device="cuda")
+    ps_g = torch.empty_like(ps_a)
+    ex = torch.empty_like(ps_a)
+    act = torch.empty(1, dtype=torch.float64, device="cuda")
+    P.pamd_action(path, pot, x, act, per_step=ps_a, tuning=tuning)
+    P.pamd_excess_action(path, pot, x, ex, tuning=tuning)
+    P.pamd_action_grad(path, pot, x, torch.empty_like(x), per_step=ps_g, tuning=tuning)
+    torch.cuda.synchronize()
+    if variant == "half":
+        assert float(((ps_a - ps_g).abs() / ps_g).max()) <= 1e-13
+    else:
+        assert torch.equal(ps_a, ps_g)
+    s0 = OS.free_step_action(X, w.D, w.dt, w.box)
+    assert np.max(np.abs(ex.cpu().numpy() - (ps_g.cpu().numpy() - s0))) <= \
+        1e-11 * float(ps_g.max())
+    assert rel(float(act.item()), math.fsum(ps_g.cpu().numpy().tolist())) <= 1e-13
