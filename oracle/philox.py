@@ -18,7 +18,10 @@ Stream layout of the sampler (key = (seed mod 2^32, seed >> 32)), for sweep s:
                  or the sin (e odd) output.
 and of the integrator's regeneration after shifting event v:
   regrowth normal  counter (p mod 2^32, p >> 32, v, 4), p and e as for trial normals
-                   (e indexes the shifted path).
+                   (e indexes the shifted path);
+and of the gradient-informed (Langevin) path move number t:
+  proposal normal  counter (p mod 2^32, p >> 32, t, 5), p and e as for trial normals
+  accept uniform   counter (0, 0, t, 6) -> uniform52(w0, w1).
 """
 from __future__ import annotations
 
@@ -34,6 +37,8 @@ PURPOSE_LEVEL = 1
 PURPOSE_ACCEPT = 2
 PURPOSE_TRIAL = 3
 PURPOSE_REGROW = 4
+PURPOSE_LANGEVIN = 5
+PURPOSE_LANGEVIN_ACCEPT = 6
 
 
 def philox4x32_10(ctr, key):
@@ -102,3 +107,13 @@ def trial_normals(seed: int, sweep: int, n_elements: int, first: int = 0,
 def regrow_normals(seed: int, event: int, n_elements: int, first: int = 0):
     """Standard normals of the regrowth after shifting event `event`."""
     return trial_normals(seed, event, n_elements, first, PURPOSE_REGROW)
+
+
+def langevin_normals(seed: int, move: int, n_elements: int, first: int = 0):
+    """Standard normals of the proposal of Langevin path move `move`."""
+    return trial_normals(seed, move, n_elements, first, PURPOSE_LANGEVIN)
+
+
+def langevin_uniform(seed: int, move: int) -> float:
+    w = philox4x32_10((0, 0, move, PURPOSE_LANGEVIN_ACCEPT), seed_key(seed))
+    return float(uniform52(w[0], w[1]))
