@@ -314,6 +314,34 @@ int pamd_run(const pamd_path* path, const pamd_potential* pot, const pamd_tuning
              void* ws, size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------------------
+ * Gradient-informed path move (an extension: the paper's moves, Sec. III, use
+ * no gradient).  One Metropolis-adjusted Langevin step in path space targeting
+ * exp(-S[X]) of Eq. 4 with x_0 fixed, using the adjoint gradient:
+ *     y = x - tau g(x) + sqrt(2 tau) z    (slices 1..N; y_0 = x_0)
+ *     log alpha = S(x) - S(y) + (|y - x + tau g(x)|^2 - |x - y + tau g(y)|^2) / (4 tau)
+ * and y replaces x when u < exp(log alpha).  z: Philox4x32-10 counter
+ * (p mod 2^32, p >> 32, t, 5), p = e >> 1 over flat element indices e of the
+ * path, Box-Muller as for trial normals; u: counter (0, 0, t, 6) ->
+ * uniform52(w0, w1); t read from *move_counter (device int64), which the call
+ * increments.  The sums run in a fixed order.
+ *   x, grad, action  device state: the path, dS/dx and S (action: 1 float64);
+ *                    the caller initialises grad and action with
+ *                    pamd_action_grad(x); on acceptance all three are updated
+ *   y, grad_y        device scratch, path-sized (the proposal and its gradient)
+ *   accepted         device int32 (1 accepted, 0 rejected), or NULL
+ *   log_alpha        device float64, or NULL
+ *   x, grad, y and grad_y must not overlap; tau > 0.
+ * Workspace: pamd_langevin_workspace_size.
+ * ---------------------------------------------------------------------- */
+int pamd_langevin_workspace_size(const pamd_path* path, const pamd_potential* pot,
+                                 const pamd_tuning* tuning, size_t* bytes);
+int pamd_langevin_step(const pamd_path* path, const pamd_potential* pot,
+                       const pamd_tuning* tuning, uint64_t seed, double tau,
+                       int64_t* move_counter, double* x, double* grad, double* action,
+                       double* y, double* grad_y, int32_t* accepted, double* log_alpha,
+                       void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
  * Sequential Euler-Maruyama integration (Eq. 2, Sec. II A): the time-stepping
  * baseline that path sampling parallelises.  Steps
  *     x_{n+1} = x_n + (dt / gamma) F(x_n) + sqrt(2 D dt) xi_n,   n = 0..N-1,

@@ -89,6 +89,10 @@ _SIGNATURES = {
     "pamd_run": (c_int32, [_PATH, _POT, _TUNE, c_uint64, c_int32, c_int32, c_int32, c_int32,
                            c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                            c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
+    "pamd_langevin_workspace_size": (c_int32, [_PATH, _POT, _TUNE, POINTER(c_size_t)]),
+    "pamd_langevin_step": (c_int32, [_PATH, _POT, _TUNE, c_uint64, c_double, c_void_p, c_void_p,
+                                     c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                                     c_void_p, c_size_t, c_void_p]),
     "pamd_em_workspace_size": (c_int32, [_PATH, _POT, _TUNE, POINTER(c_size_t)]),
     "pamd_em_integrate": (c_int32, [_PATH, _POT, _TUNE, c_void_p, c_void_p, c_void_p, c_void_p,
                                     c_size_t, c_void_p]),

@@ -23,7 +23,7 @@ __all__ = [
     "make_tuning", "pamd_workspace_size", "pamd_action", "pamd_action_grad",
     "pamd_excess_action", "pamd_log_norm", "pamd_mh_workspace_size", "pamd_mh_step",
     "pamd_em_workspace_size", "pamd_em_integrate", "pamd_shift", "pamd_run_workspace_size",
-    "pamd_run", "pamd_autotune", "PamdBatch", "PamdGraph", "workspace",
+    "pamd_run", "pamd_langevin_workspace_size", "pamd_langevin_step", "pamd_autotune", "PamdBatch", "PamdGraph", "workspace",
 ]
 
 
@@ -182,6 +182,29 @@ def pamd_run(path, pot, seed: int, l_min: int, l_max: int, n_sample: int, n_shif
               _ptr(x_alt, name="x_alt"), _ptr(trial, name="trial"), _ptr(excess, name="excess"),
               _ptr(excess_alt, name="excess_alt"), _ptr(traj_out, name="traj_out"),
               _ptr(level_stats, torch.int64, "level_stats"), _ptr(ws, None, "ws"),
+              ctypes.c_size_t(ws.numel()), _stream(stream))
+
+
+# ---------------------------------------------------------------------------
+# gradient-informed (Langevin) path move
+# ---------------------------------------------------------------------------
+def pamd_langevin_workspace_size(path, pot, tuning=None) -> int:
+    n = ctypes.c_size_t(0)
+    _lib.call("pamd_langevin_workspace_size", ctypes.byref(path), ctypes.byref(pot),
+              _ref(tuning), ctypes.byref(n))
+    return int(n.value)
+
+
+def pamd_langevin_step(path, pot, seed: int, tau: float, move_counter: torch.Tensor, x, grad,
+                       action, y, grad_y, accepted=None, log_alpha=None, ws=None, tuning=None,
+                       stream=None):
+    ws, _ = _ws(path, pot, tuning, ws, pamd_langevin_workspace_size)
+    _lib.call("pamd_langevin_step", ctypes.byref(path), ctypes.byref(pot), _ref(tuning),
+              ctypes.c_uint64(seed), ctypes.c_double(tau),
+              _ptr(move_counter, torch.int64, "move_counter"), _ptr(x, name="x"),
+              _ptr(grad, name="grad"), _ptr(action, name="action"), _ptr(y, name="y"),
+              _ptr(grad_y, name="grad_y"), _ptr(accepted, torch.int32, "accepted"),
+              _ptr(log_alpha, name="log_alpha"), _ptr(ws, None, "ws"),
               ctypes.c_size_t(ws.numel()), _stream(stream))
 
 

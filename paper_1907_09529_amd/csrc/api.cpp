@@ -791,6 +791,94 @@ int pamd_run(const pamd_path* p, const pamd_potential* v, const pamd_tuning* t, 
 }
 
 // ---------------------------------------------------------------------------
+// Gradient-informed (Langevin) path move
+// ---------------------------------------------------------------------------
+}  // extern "C"
+
+namespace {
+// The move's workspace: the action+gradient plan's, then the partial sums,
+// the proposal's action and the decision flag.
+struct LangevinPlan {
+  Plan P;
+  int blocks = 1;
+  size_t off_partial = 0, off_action = 0, off_flag = 0, total = 0;
+};
+
+int langevin_plan(const pamd_path* p, const pamd_potential* v, const pamd_tuning* t,
+                  LangevinPlan& L) {
+  int rc = make_plan(p, v, t, false, L.P);
+  if (rc) return rc;
+  const int64_t elems = p->n_steps * (int64_t)p->n_dim * p->n_atoms;
+  L.blocks = (int)std::max<int64_t>(1, std::min<int64_t>(kLangevinBlocks, (elems + 255) / 256));
+  size_t cur = L.P.total;
+  L.off_partial = bump(cur, sizeof(double) * 2 * L.blocks);
+  L.off_action = bump(cur, sizeof(double));
+  L.off_flag = bump(cur, sizeof(int32_t));
+  L.total = align_up(cur, kAlign);
+  return PAMD_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int pamd_langevin_workspace_size(const pamd_path* p, const pamd_potential* v,
+                                 const pamd_tuning* t, size_t* bytes) {
+  if (!bytes) return fail(PAMD_EINVAL, "bytes is NULL");
+  LangevinPlan L;
+  int rc = langevin_plan(p, v, t, L);
+  if (rc) return rc;
+  *bytes = L.total;
+  return PAMD_OK;
+}
+
+int pamd_langevin_step(const pamd_path* p, const pamd_potential* v, const pamd_tuning* t,
+                       uint64_t seed, double tau, int64_t* move_counter, double* x,
+                       double* grad, double* action, double* y, double* grad_y,
+                       int32_t* accepted, double* log_alpha, void* ws, size_t ws_bytes,
+                       void* stream) {
+  LangevinPlan L;
+  int rc = langevin_plan(p, v, t, L);
+  if (rc) return rc;
+  if (!std::isfinite(tau) || tau <= 0.0) return fail(PAMD_EINVAL, "tau must be finite and > 0");
+  if (!move_counter || !x || !grad || !action || !y || !grad_y)
+    return fail(PAMD_EINVAL, "move_counter, x, grad, action, y and grad_y must be non-NULL");
+  const size_t xb = sizeof(double) * (size_t)(p->n_steps + 1) * p->n_dim * p->n_atoms;
+  const double* bufs[4] = {x, grad, y, grad_y};
+  for (int i = 0; i < 4; ++i)
+    for (int j = i + 1; j < 4; ++j)
+      if (overlap(bufs[i], xb, bufs[j], xb))
+        return fail(PAMD_EINVAL, "x, grad, y and grad_y must not overlap");
+  Plan W;
+  W.total = L.total;
+  if ((rc = check_ws(W, ws, ws_bytes))) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  LangevinArgs a;
+  a.x = x;
+  a.grad = grad;
+  a.action = action;
+  a.y = y;
+  a.grad_y = grad_y;
+  a.action_y = at<double>(ws, L.off_action);
+  a.partial = at<double>(ws, L.off_partial);
+  a.flag = at<int32_t>(ws, L.off_flag);
+  a.accepted = accepted;
+  a.log_alpha = log_alpha;
+  a.counter = move_counter;
+  a.n_steps = p->n_steps;
+  a.n_dof = L.P.dof;
+  a.key0 = (uint32_t)(seed & 0xffffffffu);
+  a.key1 = (uint32_t)(seed >> 32);
+  a.tau = tau;
+  a.blocks = L.blocks;
+  PAMD_HIP(launch_langevin_propose(a, st));
+  rc = evaluate(p, v, L.P, y, nullptr, at<double>(ws, L.off_action), nullptr, grad_y, nullptr,
+                MODE_GRAD, ws, st);
+  if (rc) return rc;
+  PAMD_HIP(launch_langevin_accept(a, st));
+  return PAMD_OK;
+}
+
+// ---------------------------------------------------------------------------
 // Autotuning
 // ---------------------------------------------------------------------------
 int pamd_autotune(const pamd_path* p, const pamd_potential* v, const double* x,

@@ -236,6 +236,29 @@ struct ShiftArgs {
   double sig;            // sqrt(2 D dt)
 };
 hipError_t launch_shift(const ShiftArgs& a, hipStream_t st);
+
+// Gradient-informed (Metropolis-adjusted Langevin) path move.
+struct LangevinArgs {
+  double* x;             // current path, its gradient and action (device scalar)
+  double* grad;
+  double* action;
+  double* y;             // proposal, its gradient and action (workspace scalar)
+  double* grad_y;
+  const double* action_y;
+  double* partial;       // workspace: 2 per partial-sum block
+  int32_t* flag;         // workspace: the decision
+  int32_t* accepted;     // may be null
+  double* log_alpha;     // may be null
+  int64_t* counter;
+  int64_t n_steps;
+  int64_t n_dof;
+  uint32_t key0, key1;
+  double tau;
+  int32_t blocks;        // partial-sum blocks
+};
+constexpr int kLangevinBlocks = 512;
+hipError_t launch_langevin_propose(const LangevinArgs& a, hipStream_t st);
+hipError_t launch_langevin_accept(const LangevinArgs& a, hipStream_t st);
 hipError_t launch_copy(const double* src, double* dst, int64_t n, hipStream_t st);
 
 }  // namespace pamd

@@ -317,6 +317,105 @@ hipError_t launch_shift(const ShiftArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Gradient-informed (Metropolis-adjusted Langevin) path move
+// ---------------------------------------------------------------------------
+// y = x - tau g + sqrt(2 tau) z on slices 1..N (stream 5 of move t), y_0 = x_0.
+__global__ void langevin_propose_kernel(LangevinArgs a) {
+  const uint32_t t = (uint32_t)(*a.counter);
+  const uint64_t total = (uint64_t)(a.n_steps + 1) * a.n_dof;
+  const double amp = sqrt(2.0 * a.tau);
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; 2 * p < total; p += stride) {
+    double z[2];
+    stream_normal_pair(p, t, 5u, a.key0, a.key1, z[0], z[1]);
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const uint64_t e = 2 * p + j;
+      if (e >= total) break;
+      a.y[e] = e < (uint64_t)a.n_dof ? a.x[e] : a.x[e] - a.tau * a.grad[e] + amp * z[j];
+    }
+  }
+}
+
+// Per-block sums of |y - x + tau g|^2 and |x - y + tau g_y|^2 over slices 1..N.
+__global__ void langevin_partial_kernel(LangevinArgs a) {
+  __shared__ double red[32];
+  const int64_t total = (a.n_steps + 1) * a.n_dof;
+  double f2 = 0.0, b2 = 0.0;
+  for (int64_t e = a.n_dof + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const double d = a.y[e] - a.x[e];
+    const double f = d + a.tau * a.grad[e];
+    const double b = a.tau * a.grad_y[e] - d;
+    f2 = fma(f, f, f2);
+    b2 = fma(b, b, b2);
+  }
+  f2 = block_sum(f2, red);
+  b2 = block_sum(b2, red);
+  if (threadIdx.x == 0) {
+    a.partial[2 * blockIdx.x] = f2;
+    a.partial[2 * blockIdx.x + 1] = b2;
+  }
+}
+
+// One block: the log ratio, the uniform of move t (stream 6) and the decision.
+__global__ void langevin_decide_kernel(LangevinArgs a) {
+  __shared__ double red[32];
+  double f2 = 0.0, b2 = 0.0;
+  for (int k = threadIdx.x; k < a.blocks; k += blockDim.x) {
+    f2 += a.partial[2 * k];
+    b2 += a.partial[2 * k + 1];
+  }
+  f2 = block_sum(f2, red);
+  b2 = block_sum(b2, red);
+  if (threadIdx.x == 0) {
+    const uint32_t t = (uint32_t)(*a.counter);
+    const double la = (*a.action - *a.action_y) + (f2 - b2) / (4.0 * a.tau);
+    const U4 w = philox(0u, 0u, t, 6u, a.key0, a.key1);
+    const double u = uniform52(w.v[0], w.v[1]);
+    const int acc = u < exp(la) ? 1 : 0;
+    *a.flag = acc;
+    if (a.accepted) *a.accepted = acc;
+    if (a.log_alpha) *a.log_alpha = la;
+  }
+}
+
+// On acceptance the proposal becomes the state; the move counter advances.
+__global__ void langevin_commit_kernel(LangevinArgs a) {
+  const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t0 == 0) {
+    *a.counter += 1;
+    if (*a.flag) *a.action = *a.action_y;
+  }
+  if (!*a.flag) return;
+  const int64_t total = (a.n_steps + 1) * a.n_dof;
+  for (int64_t e = t0; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    a.x[e] = a.y[e];
+    a.grad[e] = a.grad_y[e];
+  }
+}
+
+hipError_t launch_langevin_propose(const LangevinArgs& a, hipStream_t st) {
+  const int64_t pairs = ((a.n_steps + 1) * a.n_dof + 1) / 2;
+  const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>((pairs + 255) / 256, 16384));
+  hipLaunchKernelGGL(langevin_propose_kernel, dim3((unsigned)blocks), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_langevin_accept(const LangevinArgs& a, hipStream_t st) {
+  hipLaunchKernelGGL(langevin_partial_kernel, dim3(a.blocks), dim3(256), 0, st, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(langevin_decide_kernel, dim3(1), dim3(256), 0, st, a);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int64_t total = (a.n_steps + 1) * a.n_dof;
+  const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>((total + 255) / 256, 16384));
+  hipLaunchKernelGGL(langevin_commit_kernel, dim3((unsigned)blocks), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
 hipError_t launch_copy(const double* src, double* dst, int64_t n, hipStream_t st) {
   const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 16384));
   hipLaunchKernelGGL(copy_kernel, dim3((unsigned)blocks), dim3(256), 0, st, src, dst, n);

@@ -282,3 +282,24 @@ def test_shift_and_run_validation():
     assert run(n_sample=-1) == _lib.PAMD_EINVAL
     assert run(x_alt=A) == _lib.PAMD_EINVAL
     assert run(ws_bytes=8) == _lib.PAMD_EWORKSPACE
+
+
+def test_langevin_validation():
+    lib = P.load()
+    path, pot = lj_path(), lj_pot()
+    n = ctypes.c_size_t(0)
+    assert lib.pamd_langevin_workspace_size(ctypes.byref(path), ctypes.byref(pot), None,
+                                            ctypes.byref(n)) == 0
+    assert n.value >= ws_size(path, pot)[1]
+    bufs = [ctypes.c_void_p(0x10000000 * k) for k in range(1, 5)]
+
+    def step(tau=1e-6, counter=FAKE, x=bufs[0], y=bufs[2], ws_bytes=n.value):
+        return lib.pamd_langevin_step(ctypes.byref(path), ctypes.byref(pot), None, 1,
+                                      ctypes.c_double(tau), counter, x, bufs[1], FAKE, y,
+                                      bufs[3], None, None, FAKE, ctypes.c_size_t(ws_bytes), None)
+
+    assert step(tau=0.0) == _lib.PAMD_EINVAL
+    assert step(tau=float("nan")) == _lib.PAMD_EINVAL
+    assert step(counter=None) == _lib.PAMD_EINVAL
+    assert step(y=bufs[0]) == _lib.PAMD_EINVAL
+    assert step(ws_bytes=n.value - 1) == _lib.PAMD_EWORKSPACE
