@@ -149,7 +149,8 @@ def _parser():
     ap.add_argument("--workload", default="lj864",
                     help="lj864 (default), lj108, lj27, ho1d, batch64, sweep4000, "
                          "em864 or em27 (sequential Euler-Maruyama integration), "
-                         "pamd864 or pamd27 (the path-based integration loop)")
+                         "pamd864 or pamd27 (the path-based integration loop), "
+                         "langevin864 (gradient-informed path move)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--list", choices=["auto", "full", "half"], default="auto")
@@ -198,6 +199,8 @@ def main(argv=None) -> int:
         return bench_em(args, W.workload("lj" + args.workload[2:]))
     if args.workload in ("pamd864", "pamd27"):
         return bench_pamd(args, W.workload("lj" + args.workload[4:]))
+    if args.workload == "langevin864":
+        return bench_langevin(args, W.workload("lj864"))
     w = W.workload(args.workload)
     if w.potential == "harmonic":
         return bench_harmonic(args, w)
@@ -782,6 +785,81 @@ def bench_pamd(args, w) -> int:
                                      for l in range(31) if st[l, 0] > 0}
     _line(md_rate, ms, args, "f64", config, roof, baseline, metric="md_time_per_wall_s",
           unit="md_time/s")
+    return 0
+
+
+def bench_langevin(args, w, tau: float = 1e-7) -> int:
+    """The gradient-informed path move on the benchmark path (864 atoms x
+    4096 steps): one step = one pamd_langevin_step (proposal, action and
+    gradient of the proposal, fixed-order Metropolis-Hastings test, commit),
+    replayed from a captured graph."""
+    print(f"[bench] generating {w.name}: {w.n_steps} steps x {w.n_atoms} atoms", file=sys.stderr,
+          flush=True)
+    X = W.tethered_path(w)
+    import torch
+    import paper_1907_09529_amd as P
+    P.load()
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    path = P.make_path(w.n_steps, w.n_atoms, 3, w.dt, w.D, w.gamma, "fp64")
+    pot = P.make_potential("lj", eps=w.eps, sigma=w.sigma, rc=w.cutoff, box=w.box)
+    x = torch.from_numpy(X).to(dev)
+    g, y, gy = torch.empty_like(x), torch.empty_like(x), torch.empty_like(x)
+    S = torch.empty(1, dtype=torch.float64, device=dev)
+    P.pamd_action_grad(path, pot, x, g, action=S)
+    counter = torch.zeros(1, dtype=torch.int64, device=dev)
+    acc = torch.zeros(1, dtype=torch.int32, device=dev)
+    ws = P.workspace(P.pamd_langevin_workspace_size(path, pot))
+    s = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    gr = P.PamdGraph()
+    with torch.cuda.stream(s):
+        gr.begin(s)
+        P.pamd_langevin_step(path, pot, 0x5EED1907, tau, counter, x, g, S, y, gy, acc, ws=ws,
+                             stream=s)
+        gr.end(s)
+        for _ in range(args.warmup):
+            gr.launch(s)
+    s.synchronize()
+    ev = HipEvents()
+    t0 = time.perf_counter()
+    HipEvents.hip.hipEventRecord(ev.a, ctypes.c_void_p(s.cuda_stream))
+    for _ in range(args.steps):
+        gr.launch(s)
+    HipEvents.hip.hipEventRecord(ev.b, ctypes.c_void_p(s.cuda_stream))
+    s.synchronize()
+    t1 = time.perf_counter()
+    ms = (t1 - t0) * 1e3 / args.steps
+    ev.close()
+    # acceptance over as many further moves, read back one by one (untimed)
+    n_acc = 0
+    for _ in range(args.steps):
+        gr.launch(s)
+        s.synchronize()
+        n_acc += int(acc.item())
+    gr.close()
+    lib = P.load()
+    kev = [HipEvents() for _ in range(3)]
+    for e in kev:
+        lib.pamd_profile_events(e.a, e.b)
+        P.pamd_action_grad(path, pot, y, gy)
+    k_ms = float(np.mean([e.elapsed_ms() for e in kev]))
+    for e in kev:
+        e.close()
+    ppa = pairs_per_atom(X, w.box, w.cutoff)
+    flop_unit = ppa * (FLOP_FORCE_PAIR + FLOP_HV_PAIR) + FLOP_SLICE_ATOM
+    units = w.n_steps * w.n_atoms
+    achieved = flop_unit * units / (k_ms * 1e-3)
+    roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64_VALU / 1e12,
+            "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VALU, "traffic": None,
+            "kernel": "lj_fused_kernel (action + gradient of the proposal)", "kernel_ms": k_ms,
+            "flop_per_slice_atom": flop_unit, "pairs_per_atom": ppa}
+    config = {"workload": f"gradient-informed path move, LJ {w.n_atoms} atoms x {w.n_steps} steps, "
+                          f"tau {tau:g}, graph-replayed moves (tethered-lattice start path)",
+              "n_atoms": w.n_atoms, "n_steps": w.n_steps, "tau": tau,
+              "acceptance": n_acc / args.steps, "parallelism": "single GPU"}
+    _line(units / (ms * 1e-3), ms, args, "f64", config, roof, None,
+          metric="langevin_move_slice_atoms_per_s", unit="slice_atoms/s")
     return 0
 
 
