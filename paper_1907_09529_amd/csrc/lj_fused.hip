@@ -247,11 +247,17 @@ __device__ __forceinline__ int row_capacity(int kmax) {
   return HALF ? kmax : ((kmax / 2 + 15) & ~7);
 }
 
-// (Re)builds the neighbour lists (radius^2 rl2, box units) of the slice in
-// L.X.  With cells, atoms are first re-sorted into cell order (slots and perm
-// are rewritten).
+// (Re)builds the neighbour lists of the slice in L.X (box units).  With cells,
+// atoms are first re-sorted into cell order (slots and perm are rewritten).
+// With rho in LDS (XS == XS_R) a pair is listed when its distance is at most
+// rcm + d_i + d_j, with the per-atom reach d taken from dsrc (by original atom
+// index; LDS) or, when dsrc is null, dconst for every atom; the reaches are
+// parked in slot element 3 for the scan (free until pass 1 stores rho).
+// Otherwise the radius^2 is rl2.  scan_radius() of the caller keeps both forms
+// conservative (a relative 1e-12 margin).
 template <int XS, bool HALF>
-__device__ void rebuild(const PathArgs& a, const TileLDS& L, const TileScratch& ts, double rl2) {
+__device__ void rebuild(const PathArgs& a, const TileLDS& L, const TileScratch& ts, double rl2,
+                        double rcm, const lds_f64* dsrc, double dconst) {
   constexpr int PARTS = HALF ? 1 : 2;
   constexpr int SPAN = WAVE / PARTS;  // slots per wave
   const int N = a.n_atoms;
@@ -287,6 +293,10 @@ __device__ void rebuild(const PathArgs& a, const TileLDS& L, const TileScratch& 
     }
     __syncthreads();
   }
+  if constexpr (XS == XS_R) {
+    for (int s = threadIdx.x; s < N; s += B) L.X[XS * L.pos(s) + 3] = dsrc ? dsrc[L.perm[s]] : dconst;
+    __syncthreads();  // every reach parked
+  }
   const int nc = a.nc, reach = a.reach;
   const int lane = threadIdx.x & (WAVE - 1);
   const int part = PARTS == 1 ? 0 : lane / SPAN;
@@ -308,6 +318,7 @@ __device__ void rebuild(const PathArgs& a, const TileLDS& L, const TileScratch& 
     const int sc = live ? s : base;
     const int me = L.pos(sc);
     const double xs = L.X[XS * me], ys = L.X[XS * me + 1], zs = L.X[XS * me + 2];
+    const double rme = XS == XS_R ? rcm + L.X[XS * me + 3] : 0.0;  // rc + own reach
     uint16_t* nb = ts.nbr;
     const uint32_t wbase = 8u * (uint32_t)(PARTS * sc + part);
     const uint32_t wcap = wbase + cap;
@@ -344,13 +355,21 @@ __device__ void rebuild(const PathArgs& a, const TileLDS& L, const TileScratch& 
         uint32_t bits = 0;
         for (int j = 0; j < 32; j += 4) {
           if (g + j >= nmax) break;
-          double px[4], py[4], pz[4];
+          double px[4], py[4], pz[4], pd[4];
 #pragma unroll
           for (int u = 0; u < 4; ++u) {
             const int p = min(p0 + g + j + u, plast);
-            px[u] = L.X[XS * p + 0];
-            py[u] = L.X[XS * p + 1];
-            pz[u] = L.X[XS * p + 2];
+            if constexpr (XS == XS_R) {
+              const f64x2 xy = lds_ld2(L.X + XS * p), zd = lds_ld2(L.X + XS * p + 2);
+              px[u] = xy.x;
+              py[u] = xy.y;
+              pz[u] = zd.x;
+              pd[u] = zd.y;
+            } else {
+              px[u] = L.X[XS * p + 0];
+              py[u] = L.X[XS * p + 1];
+              pz[u] = L.X[XS * p + 2];
+            }
           }
 #pragma unroll
           for (int u = 0; u < 4; ++u) {
@@ -359,7 +378,12 @@ __device__ void rebuild(const PathArgs& a, const TileLDS& L, const TileScratch& 
             const double dy = wrap_u(ys - py[u]);
             const double dz = wrap_u(zs - pz[u]);
             const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
-            const bool pass = k < np && p0 + k != me && r2 <= rl2 &&
+            double lim2 = rl2;
+            if constexpr (XS == XS_R) {
+              const double lim = rme + pd[u];
+              lim2 = lim * lim;
+            }
+            const bool pass = k < np && p0 + k != me && r2 <= lim2 &&
                               (!HALF || upper_half(dx, dy, dz, s, p0 + k));
             bits |= pass ? (1u << (j + u)) : 0u;
           }
@@ -841,11 +865,17 @@ __device__ __forceinline__ void tile_body(const PathArgs& a, int tile, const Til
   // that comes within r_c anywhere in the tile, and no slice asks for new
   // lists.  When D2 exceeds (skin/2)^2 the configured skin applies and slices
   // that move further get new lists.
+  //
+  // With rho in LDS the bound is per atom: atom i strays at most d_i from its
+  // middle-slice position, so a pair is listed when its distance there is at
+  // most r_c + d_i + d_j (the reaches wait in the second slot array, which
+  // the first slice load has not used yet).
   double d2max = 0.0;
   for (int i = threadIdx.x; i < N; i += B) {
     double ur[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) ur[c] = a.x[(size_t)nref * slice + (size_t)c * N + i] * ib;
+    double di2 = 0.0;
     for (int64_t m = n0; m < n1; ++m) {
       double d2 = 0.0;
 #pragma unroll
@@ -853,21 +883,30 @@ __device__ __forceinline__ void tile_body(const PathArgs& a, int tile, const Til
         const double du = wrap_u(a.x[(size_t)m * slice + (size_t)c * N + i] * ib - ur[c]);
         d2 = fma(du, du, d2);
       }
-      d2max = fmax(d2max, d2);
+      di2 = fmax(di2, d2);
     }
+    if constexpr (RLDS) L.X2[i] = di2;
+    d2max = fmax(d2max, di2);
   }
   d2max = block_max_all(d2max, L.red);
+  const double rcm = sqrt(a.bu.rc2) * (1.0 + 1e-12);
+  const lds_f64* reach = nullptr;
   if (d2max <= hs2) {
     hs2 = d2max;
     const double r = sqrt(a.bu.rc2) + 2.0 * sqrt(d2max);
     rl2 = r * r * (1.0 + 1e-12);
+    if constexpr (RLDS) {
+      for (int i = threadIdx.x; i < N; i += B) L.X2[i] = sqrt(L.X2[i]) * (1.0 + 1e-12);
+      reach = L.X2;
+    }
   }
+  const double reach_all = 0.5 * (sqrt(rl2) - rcm);  // every atom's reach at radius sqrt(rl2)
   bool first = true;  // X holds the middle slice, whose lists come first
 
   for (int64_t n = n0; n < n1;) {
     __syncthreads();  // X holds x_n (or the middle slice); flag[n & 1] is final
     if (first || L.flag[n & 1]) {
-      rebuild<XS, HALF>(a, L, ts, rl2);
+      rebuild<XS, HALF>(a, L, ts, rl2, rcm, first ? reach : nullptr, reach_all);
       __syncthreads();  // lists and slots ready
       if (first) {
         // x_n0 in the new slot order; it may itself need new lists
@@ -1188,7 +1227,8 @@ __global__ void __launch_bounds__(1024) lj_em_kernel(PathArgs a, const double* x
   for (int64_t n = 0; n < a.n_steps; ++n) {
     __syncthreads();  // X and x_out hold x_n; flag[n & 1] is final
     if (first || L.flag[n & 1]) {
-      rebuild<XS, false>(a, L, ts, rl2);
+      const double rcm = sqrt(a.bu.rc2) * (1.0 + 1e-12);
+      rebuild<XS, false>(a, L, ts, rl2, rcm, nullptr, 0.5 * (sqrt(rl2) - rcm));
       __syncthreads();  // lists and slots ready
       first = false;
     }
