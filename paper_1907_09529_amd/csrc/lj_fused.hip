@@ -844,51 +844,51 @@ __device__ __forceinline__ void tile_body(const PathArgs& a, int tile, const Til
     if (!(dmax <= hs2)) L.flag[m & 1] = 1;
   };
 
-  // The tile's first lists are built from its middle slice: every slice of
-  // the tile is then at most half a tile away from the build positions, which
-  // keeps atoms within skin/2 of them for twice as many steps as lists built
-  // at the tile's first slice.
-  const int64_t nref = n0 + (n1 - n0) / 2;
-  for (int i = threadIdx.x; i < N; i += B) {
-    L.perm[i] = (uint16_t)i;
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      L.X[XS * L.pos(i) + c] = a.x[(size_t)nref * slice + (size_t)c * N + i] * ib;
-      ts.rprev[3 * i + c] = 0.0;
-    }
-  }
-  if (threadIdx.x == 0) L.flag[0] = L.flag[1] = 0;
-  // List radius for this tile.  D2, the largest squared displacement of any
-  // atom from the middle slice over the force-evaluated slices n0 .. n1 - 1
-  // (box units, the same arithmetic as load_slice's test), bounds how far a
-  // pair distance moves: lists of radius r_c + 2 sqrt(D2) hold every pair
-  // that comes within r_c anywhere in the tile, and no slice asks for new
-  // lists.  When D2 exceeds (skin/2)^2 the configured skin applies and slices
-  // that move further get new lists.
+  // The tile's first lists are built around each atom's centre: the middle
+  // of the box that bounds its positions over the force-evaluated slices
+  // n0 .. n1 - 1 (box units, coordinates unwrapped).  Every position of
+  // atom i then lies within d_i, half the box's diagonal, of that centre, so
+  // a pair's distance differs from the distance of the centres by at most
+  // d_i + d_j.  D2 = max d_i^2 bounds the displacement test of load_slice:
+  // lists of radius r_c + 2 sqrt(D2) hold every pair that comes within r_c
+  // anywhere in the tile, and no slice asks for new lists.  When D2 exceeds
+  // (skin/2)^2 the configured skin applies instead and slices that move
+  // further get new lists.
   //
-  // With rho in LDS the bound is per atom: atom i strays at most d_i from its
-  // middle-slice position, so a pair is listed when its distance there is at
-  // most r_c + d_i + d_j (the reaches wait in the second slot array, which
-  // the first slice load has not used yet).
+  // With rho in LDS the bound is per atom: a pair is listed when its centres
+  // are at most r_c + d_i + d_j apart (the reaches wait in the second slot
+  // array, which the first slice load has not used yet).
   double d2max = 0.0;
   for (int i = threadIdx.x; i < N; i += B) {
-    double ur[3];
+    L.perm[i] = (uint16_t)i;
+    double lo[3], hi[3];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) ur[c] = a.x[(size_t)nref * slice + (size_t)c * N + i] * ib;
-    double di2 = 0.0;
-    for (int64_t m = n0; m < n1; ++m) {
-      double d2 = 0.0;
+    for (int c = 0; c < 3; ++c) {
+      lo[c] = hi[c] = a.x[(size_t)n0 * slice + (size_t)c * N + i] * ib;
+      ts.rprev[3 * i + c] = 0.0;
+    }
+    for (int64_t m = n0 + 1; m < n1; ++m) {
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        const double du = wrap_u(a.x[(size_t)m * slice + (size_t)c * N + i] * ib - ur[c]);
-        d2 = fma(du, du, d2);
+        const double u = a.x[(size_t)m * slice + (size_t)c * N + i] * ib;
+        lo[c] = fmin(lo[c], u);
+        hi[c] = fmax(hi[c], u);
       }
-      di2 = fmax(di2, d2);
+    }
+    double di2 = 0.0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const double h = 0.5 * (hi[c] - lo[c]);
+      di2 = fma(h, h, di2);
+      L.X[XS * L.pos(i) + c] = 0.5 * (hi[c] + lo[c]);
     }
     if constexpr (RLDS) L.X2[i] = di2;
     d2max = fmax(d2max, di2);
   }
-  d2max = block_max_all(d2max, L.red);
+  if (threadIdx.x == 0) L.flag[0] = L.flag[1] = 0;
+  // (rounding of the centres and of the test's differences stays far inside
+  // the relative 1e-10 on D2 and 1e-12 on the reaches)
+  d2max = block_max_all(d2max, L.red) * (1.0 + 1e-10);
   const double rcm = sqrt(a.bu.rc2) * (1.0 + 1e-12);
   const lds_f64* reach = nullptr;
   if (d2max <= hs2) {
@@ -901,10 +901,10 @@ __device__ __forceinline__ void tile_body(const PathArgs& a, int tile, const Til
     }
   }
   const double reach_all = 0.5 * (sqrt(rl2) - rcm);  // every atom's reach at radius sqrt(rl2)
-  bool first = true;  // X holds the middle slice, whose lists come first
+  bool first = true;  // X holds the centres, whose lists come first
 
   for (int64_t n = n0; n < n1;) {
-    __syncthreads();  // X holds x_n (or the middle slice); flag[n & 1] is final
+    __syncthreads();  // X holds x_n (or the centres); flag[n & 1] is final
     if (first || L.flag[n & 1]) {
       rebuild<XS, HALF>(a, L, ts, rl2, rcm, first ? reach : nullptr, reach_all);
       __syncthreads();  // lists and slots ready
