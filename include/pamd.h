@@ -376,10 +376,13 @@ int pamd_autotune(const pamd_path* path, const pamd_potential* pot, const double
                   pamd_tuning* best);
 
 /* ------------------------------------------------------------------------
- * Measurement hook: the next pamd_action / pamd_action_grad /
- * pamd_excess_action / pamd_em_integrate call made by this thread records `start` (a hipEvent_t)
- * on its stream just before its main kernel and `stop` just after it, so that
- * the events bracket that kernel alone.  Host-only; pass NULLs to clear.
+ * Measurement hook: the next action evaluation or integration enqueued by
+ * this thread records `start` (a hipEvent_t) on its stream just before its
+ * main kernel and `stop` just after it, so that the events bracket that kernel
+ * alone: pamd_action, pamd_action_grad, pamd_excess_action and
+ * pamd_em_integrate bracket their own kernel; pamd_mh_step, pamd_run and
+ * pamd_langevin_step bracket their first action evaluation.  Host-only; pass
+ * NULLs to clear.
  * ---------------------------------------------------------------------- */
 int pamd_profile_events(void* start, void* stop);
 
