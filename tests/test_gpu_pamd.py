@@ -187,3 +187,38 @@ def test_run_harmonic_follows_the_euler_law(device):
     assert abs(var - 1.25) < 0.06, var
     assert abs(lag1 - 0.6) < 0.03, lag1
     check_final_excess(w, x, ex)
+
+
+@pytest.mark.parametrize("n_sample,n_shift,n_events", [(0, 3, 5), (1, 16, 3), (2, 1, 4)])
+def test_run_edge_schedules(device, n_sample, n_shift, n_events):
+    """Shift-only events (no sampling), a shift of the whole path (the scheme
+    of Fig. 1: every slice regrown) and single-step shifts."""
+    w = dataclasses.replace(W.workload("ho1d"), n_steps=16, n_atoms=3, dt=0.4)
+    X = exact_paths_ho(np.random.default_rng(12), 16, 3)
+    T, x, ex, counters = run_gpu(w, X, 77, 2, 3, n_sample, n_shift, n_events)
+    T_ref, X_ref = OP.run(X, oracle_pot(w), w.dt, w.D, w.gamma, 77, 2, 3, n_sample, n_shift,
+                          n_events)
+    assert np.max(np.abs(T - T_ref)) <= 1e-10
+    assert np.max(np.abs(x.cpu().numpy() - X_ref)) <= 1e-10
+    assert list(counters) == [n_sample * n_events, n_events]
+    check_final_excess(w, x, ex)
+
+
+def test_shift_without_excess_or_trajectory(device):
+    path = P.make_path(8, 2, 1, 0.1, 1.0, 1.0)
+    X = np.random.default_rng(3).standard_normal((9, 1, 2))
+    x_in = dev(X)
+    x_out = torch.empty_like(x_in)
+    counter = torch.zeros(1, dtype=torch.int64, device="cuda")
+    P.pamd_shift(path, 5, 3, counter, x_in, x_out)
+    torch.cuda.synchronize()
+    ref = OP.shift_path(X, 3, OP.regrowth_normals(5, 0, X.shape, 3), 1.0, 0.1)
+    assert np.max(np.abs(x_out.cpu().numpy() - ref)) <= 1e-12
+    assert int(counter.item()) == 1
+
+
+def exact_paths_ho(rng, n_steps, n_dof):
+    X = np.zeros((n_steps + 1, 1, n_dof))
+    for n in range(n_steps):
+        X[n + 1] = 0.6 * X[n] + math.sqrt(0.8) * rng.standard_normal((1, n_dof))
+    return X
