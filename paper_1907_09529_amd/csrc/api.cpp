@@ -164,6 +164,7 @@ struct Plan {
   CellGrid cells;
   double skin = 0;
   bool r_in_lds = true;
+  bool lds2 = true;  // with r_in_lds: two slot arrays
   bool half = false;
   size_t lds = 0;
   // plain LJ
@@ -223,11 +224,17 @@ int make_plan(const pamd_path* p, const pamd_potential* v, const pamd_tuning* t_
     P.half = list == PAMD_LIST_HALF;  // automatic choice: full lists (repeatable, as fast)
     if (P.half && N > fused_half_slots() * P.block)
       return fail(PAMD_EUNSUPPORTED, "half lists need n_atoms <= %d * block", fused_half_slots());
-    // residuals in LDS (two slot arrays) when they fit, else in global scratch
-    if (fused_cells_fit(L, radius, N, P.block, true, P.half, &P.cells, &P.lds)) {
+    // residuals in LDS with two slot arrays when they fit, else with one,
+    // else in global scratch
+    if (fused_cells_fit(L, radius, N, P.block, true, P.half, &P.cells, &P.lds, true)) {
       P.r_in_lds = true;
+      P.lds2 = true;
+    } else if (fused_cells_fit(L, radius, N, P.block, true, P.half, &P.cells, &P.lds, false)) {
+      P.r_in_lds = true;
+      P.lds2 = false;
     } else if (fused_cells_fit(L, radius, N, P.block, false, P.half, &P.cells, &P.lds)) {
       P.r_in_lds = false;
+      P.lds2 = false;
     } else {
       return fail(PAMD_EUNSUPPORTED, "n_atoms = %d needs %zu bytes of LDS per workgroup (max %zu)", N,
                   fused_lds_bytes(N, 0, false, P.half, P.block), kLdsMax);
@@ -254,7 +261,9 @@ int make_plan(const pamd_path* p, const pamd_potential* v, const pamd_tuning* t_
     P.nbr_stride = 2 * align_up((size_t)(P.kmax + 32) * N, 128);
     P.cnt_stride = align_up((size_t)2 * N, 64);  // list lengths: up to two rows per atom
     P.xref_stride = align_up((size_t)6 * N, 32);
-    P.rglob_stride = P.r_in_lds ? 0 : align_up((size_t)3 * N, 32);
+    // global scratch: residuals, or with one LDS slot array the list reaches
+    // (and the sequential integrator's sort scratch)
+    P.rglob_stride = P.r_in_lds && P.lds2 ? 0 : align_up((size_t)3 * N, 32);
     P.off_nbr = bump(cur, sizeof(uint16_t) * P.nbr_stride * P.grid);
     P.off_cnt = bump(cur, sizeof(int32_t) * P.cnt_stride * P.grid);
     P.off_xref = bump(cur, sizeof(double) * P.xref_stride * P.grid);
@@ -320,6 +329,7 @@ void fill_lj(const pamd_path* p, const pamd_potential* v, const Plan& P, PathArg
   a.nc = P.cells.nc;
   a.reach = P.cells.reach;
   a.kmax = P.kmax;
+  a.lds2 = P.r_in_lds && P.lds2 ? 1 : 0;
   set_box_units(a);
 }
 
@@ -328,7 +338,7 @@ BlockScratch scratch_of(const Plan& P, void* ws) {
   s.nbr = at<uint16_t>(ws, P.off_nbr);
   s.cnt = at<int32_t>(ws, P.off_cnt);
   s.xref = at<double>(ws, P.off_xref);
-  s.rglob = P.r_in_lds ? nullptr : at<double>(ws, P.off_rglob);
+  s.rglob = P.rglob_stride ? at<double>(ws, P.off_rglob) : nullptr;
   s.nbr_stride = (int64_t)P.nbr_stride;
   s.cnt_stride = (int64_t)P.cnt_stride;
   s.xref_stride = (int64_t)P.xref_stride;
@@ -341,6 +351,7 @@ FusedLaunch launch_of(const Plan& P) {
   L.block = P.block;
   L.grid = P.grid;
   L.r_in_lds = P.r_in_lds;
+  L.lds2 = P.lds2;
   L.f32 = P.f32;
   L.half = P.half;
   L.lds_bytes = P.lds;
@@ -432,11 +443,11 @@ CellGrid choose_cells(double box, double radius, int n_atoms, int max_cells) {
 }
 
 bool fused_cells_fit(double box, double radius, int n_atoms, int block, bool r_in_lds, bool half,
-                     CellGrid* grid, size_t* lds) {
+                     CellGrid* grid, size_t* lds, bool two) {
   int cap = 1 << 30;
   for (;;) {
     const CellGrid g = choose_cells(box, radius, n_atoms, cap);
-    const size_t b = fused_lds_bytes(n_atoms, g.nc, r_in_lds, half, block);
+    const size_t b = fused_lds_bytes(n_atoms, g.nc, r_in_lds, half, block, two);
     if (b <= kFusedLdsMax) {
       *grid = g;
       *lds = b;

@@ -179,26 +179,29 @@ int pamd_batch_create(int32_t n_paths, const pamd_path* paths, const pamd_potent
       delete b;
       return batch_fail(PAMD_EUNSUPPORTED, "half lists do not fit this batch");
     }
-    // one residual placement for the whole batch: in LDS if every member
-    // fits so, else in global scratch; each member gets the finest cell grid
-    // that fits
-    auto fit_all = [&](bool r_in_lds) {
+    // one residual placement for the whole batch: in LDS with two slot
+    // arrays if every member fits so, else with one, else in global scratch;
+    // each member gets the finest cell grid that fits
+    auto fit_all = [&](bool r_in_lds, bool two) {
       size_t lds_max = 0;
       for (size_t mi = 0; mi < b->members.size(); ++mi) {
         PathArgs& a = b->members[mi].a;
         CellGrid g;
         size_t lds = 0;
-        if (!fused_cells_fit(a.lj.box, radii[mi], a.n_atoms, L.block, r_in_lds, L.half, &g, &lds))
+        if (!fused_cells_fit(a.lj.box, radii[mi], a.n_atoms, L.block, r_in_lds, L.half, &g, &lds,
+                             two))
           return false;
         a.nc = g.nc;
         a.reach = g.reach;
+        a.lds2 = r_in_lds && two ? 1 : 0;
         lds_max = std::max(lds_max, lds);
       }
       L.r_in_lds = r_in_lds;
+      L.lds2 = r_in_lds && two;
       L.lds_bytes = lds_max;
       return true;
     };
-    if (!fit_all(true) && !fit_all(false)) {
+    if (!fit_all(true, true) && !fit_all(true, false) && !fit_all(false, false)) {
       delete b;
       return batch_fail(PAMD_EUNSUPPORTED, "batch member with %d atoms exceeds LDS", max_n);
     }
@@ -207,7 +210,7 @@ int pamd_batch_create(int32_t n_paths, const pamd_path* paths, const pamd_potent
   b->nbr_stride = 2 * align_up(max_nbr, 128);  // neighbour list + exact list
   b->cnt_stride = align_up((size_t)2 * max_n, 64);  // list lengths: up to two rows per atom
   b->xref_stride = align_up((size_t)6 * max_n, 32);
-  b->rglob_stride = L.r_in_lds ? 0 : align_up((size_t)3 * max_n, 32);
+  b->rglob_stride = L.r_in_lds && L.lds2 ? 0 : align_up((size_t)3 * max_n, 32);
   size_t cur = 0;
   b->off_members = bump(cur, sizeof(BatchMember) * std::max<size_t>(1, b->members.size()));
   b->off_slots = bump(cur, sizeof(int32_t) * std::max<size_t>(1, b->slots.size()));
@@ -281,7 +284,7 @@ int pamd_batch_action_grad(const pamd_batch* b, const double* x_all, const doubl
     s.nbr = (uint16_t*)(base + b->off_nbr);
     s.cnt = (int32_t*)(base + b->off_cnt);
     s.xref = (double*)(base + b->off_xref);
-    s.rglob = b->launch.r_in_lds ? nullptr : (double*)(base + b->off_rglob);
+    s.rglob = b->rglob_stride ? (double*)(base + b->off_rglob) : nullptr;
     s.nbr_stride = (int64_t)b->nbr_stride;
     s.cnt_stride = (int64_t)b->cnt_stride;
     s.xref_stride = (int64_t)b->xref_stride;

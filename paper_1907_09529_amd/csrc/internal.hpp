@@ -60,7 +60,7 @@ struct PathArgs {
   int32_t nc;             // cells per axis (0: all pairs)
   int32_t reach;          // stencil half-width in cells
   int32_t kmax;           // list capacity per atom
-  int32_t pad0;
+  int32_t lds2;           // rho in LDS with two slot arrays (1) or one (0)
   BoxUnits bu;            // set by set_box_units() from lj, rlist2 and half_skin2
 };
 
@@ -101,6 +101,7 @@ struct FusedLaunch {
   int block;        // threads per block
   int grid;         // blocks
   bool r_in_lds;
+  bool lds2;        // with r_in_lds: two slot arrays (else one)
   bool f32;
   bool half;        // half neighbour lists with LDS atomics (else full lists)
   size_t lds_bytes;
@@ -133,7 +134,8 @@ struct BatchBase {
 };
 
 // Shared memory of the fused kernel's workgroup (bytes).
-size_t fused_lds_bytes(int n_atoms, int nc, bool r_in_lds, bool half, int block);
+// With rho in LDS (r_in_lds) there are two slot arrays (two) or one.
+size_t fused_lds_bytes(int n_atoms, int nc, bool r_in_lds, bool half, int block, bool two = true);
 int fused_half_slots();
 constexpr size_t kFusedLdsMax = 163840;  // LDS per workgroup on gfx950
 
@@ -149,7 +151,7 @@ CellGrid choose_cells(double box, double radius, int n_atoms, int max_cells);
 // The finest cell grid with which the fused kernel's LDS (given block size,
 // residual placement and list kind) fits kFusedLdsMax; false if none does.
 bool fused_cells_fit(double box, double radius, int n_atoms, int block, bool r_in_lds, bool half,
-                     CellGrid* grid, size_t* lds);
+                     CellGrid* grid, size_t* lds, bool two = true);
 size_t plain_lds_bytes(int n_atoms, int nc);
 
 hipError_t launch_lj_fused(const PathArgs& a, const BlockScratch& s, const FusedLaunch& L,

@@ -55,9 +55,10 @@ constexpr int EX_PAD = 32;     // exact-list entries per atom beyond kmax (see T
 
 // Shared-memory layout of one tile.  With rho in LDS every slot holds
 // XS_R = 6 doubles, its position u (0..2) and rho (3..5), read as three
-// 16-byte loads, and there are two slot arrays: slice n + 1 is loaded into one
-// while pass 2 of slice n reads the other.  (16-byte LDS loads move about 1.6x
-// the bytes per clock of 8-byte ones at scattered addresses on gfx950.)
+// 16-byte loads, and there are two slot arrays when they fit: slice n + 1 is
+// loaded into one while pass 2 of slice n reads the other; with one array the
+// next slice is loaded after pass 2.  (16-byte LDS loads move about 1.6x the
+// bytes per clock of 8-byte ones at scattered addresses on gfx950.)
 // Otherwise a slot holds 3 doubles (positions only; rho lives in global
 // scratch) and there is one array.
 constexpr int XS_R = 6;
@@ -96,7 +97,7 @@ __host__ __device__ inline uint32_t lds_shared_region(int n_atoms, int ncell, in
 }
 
 __device__ inline TileLDS carve_lds(char* base_generic, int n_atoms, int ncell, bool r_in_lds,
-                                    bool half) {
+                                    bool half, bool two) {
   typedef __attribute__((address_space(3))) char lds_char;
   lds_char* base = (lds_char*)base_generic;
   TileLDS t;
@@ -107,7 +108,7 @@ __device__ inline TileLDS carve_lds(char* base_generic, int n_atoms, int ncell, 
     return p;
   };
   t.X = f64((uint32_t)(r_in_lds ? XS_R : 3) * n_atoms);
-  t.X2 = r_in_lds ? f64((uint32_t)XS_R * n_atoms) : t.X;
+  t.X2 = r_in_lds && two ? f64((uint32_t)XS_R * n_atoms) : t.X;
   t.ACC = half ? f64(3u * n_atoms) : nullptr;
   t.red = f64(32);
   t.tmp = (lds_i32*)(base + off);
@@ -127,9 +128,10 @@ __device__ inline TileLDS carve_lds(char* base_generic, int n_atoms, int ncell, 
   return t;
 }
 
-size_t fused_lds_bytes(int n_atoms, int nc, bool r_in_lds, bool half, int block) {
+size_t fused_lds_bytes(int n_atoms, int nc, bool r_in_lds, bool half, int block, bool two) {
   const size_t ncell = (size_t)nc * nc * nc;
-  size_t b = sizeof(double) * (size_t)n_atoms * ((r_in_lds ? 2 * XS_R : 3) + (half ? 3 : 0));
+  const size_t slots = r_in_lds ? (two ? 2 * XS_R : XS_R) : 3;
+  size_t b = sizeof(double) * (size_t)n_atoms * (slots + (half ? 3 : 0));
   b += sizeof(double) * 32 + sizeof(int) * 18 + 6 * (size_t)n_atoms + 16;
   b += lds_shared_region(n_atoms, (int)ncell, block);
   return b;
@@ -251,13 +253,13 @@ __device__ __forceinline__ int row_capacity(int kmax) {
 // atoms are first re-sorted into cell order (slots and perm are rewritten).
 // With rho in LDS (XS == XS_R) a pair is listed when its distance is at most
 // rcm + d_i + d_j, with the per-atom reach d taken from dsrc (by original atom
-// index; LDS) or, when dsrc is null, dconst for every atom; the reaches are
+// index) or, when dsrc is null, dconst for every atom; the reaches are
 // parked in slot element 3 for the scan (free until pass 1 stores rho).
 // Otherwise the radius^2 is rl2.  scan_radius() of the caller keeps both forms
 // conservative (a relative 1e-12 margin).
 template <int XS, bool HALF>
 __device__ void rebuild(const PathArgs& a, const TileLDS& L, const TileScratch& ts, double rl2,
-                        double rcm, const lds_f64* dsrc, double dconst) {
+                        double rcm, const double* dsrc, double dconst) {
   constexpr int PARTS = HALF ? 1 : 2;
   constexpr int SPAN = WAVE / PARTS;  // slots per wave
   const int N = a.n_atoms;
@@ -794,10 +796,10 @@ template <bool F32, bool RLDS, bool HALF, bool GRAD = true>
 __device__ __forceinline__ void tile_body(const PathArgs& a, int tile, const TileScratch& ts,
                                           char* lds_base) {
   constexpr int XS = RLDS ? XS_R : 3;  // LDS doubles per slot
-  constexpr bool DB = RLDS;         // two slot arrays (see TileLDS)
+  const bool DB = RLDS && a.lds2;      // two slot arrays (see TileLDS)
   const int N = a.n_atoms;
   const int ncell = a.nc * a.nc * a.nc;
-  TileLDS L = carve_lds(lds_base, N, ncell, RLDS, HALF);
+  TileLDS L = carve_lds(lds_base, N, ncell, RLDS, HALF, DB);
   const int64_t n0 = (int64_t)tile * a.tile;
   const int64_t n1 = min(n0 + (int64_t)a.tile, a.n_steps);
   const size_t slice = (size_t)3 * N;
@@ -857,7 +859,8 @@ __device__ __forceinline__ void tile_body(const PathArgs& a, int tile, const Til
   //
   // With rho in LDS the bound is per atom: a pair is listed when its centres
   // are at most r_c + d_i + d_j apart (the reaches wait in the second slot
-  // array, which the first slice load has not used yet).
+  // array, which the first slice load has not used yet, or with one array in
+  // global scratch).
   double d2max = 0.0;
   for (int i = threadIdx.x; i < N; i += B) {
     L.perm[i] = (uint16_t)i;
@@ -882,7 +885,12 @@ __device__ __forceinline__ void tile_body(const PathArgs& a, int tile, const Til
       di2 = fma(h, h, di2);
       L.X[XS * L.pos(i) + c] = 0.5 * (hi[c] + lo[c]);
     }
-    if constexpr (RLDS) L.X2[i] = di2;
+    if constexpr (RLDS) {
+      if (DB)
+        L.X2[i] = di2;
+      else
+        ts.rglob[i] = di2;
+    }
     d2max = fmax(d2max, di2);
   }
   if (threadIdx.x == 0) L.flag[0] = L.flag[1] = 0;
@@ -890,14 +898,19 @@ __device__ __forceinline__ void tile_body(const PathArgs& a, int tile, const Til
   // the relative 1e-10 on D2 and 1e-12 on the reaches)
   d2max = block_max_all(d2max, L.red) * (1.0 + 1e-10);
   const double rcm = sqrt(a.bu.rc2) * (1.0 + 1e-12);
-  const lds_f64* reach = nullptr;
+  const double* reach = nullptr;
   if (d2max <= hs2) {
     hs2 = d2max;
     const double r = sqrt(a.bu.rc2) + 2.0 * sqrt(d2max);
     rl2 = r * r * (1.0 + 1e-12);
     if constexpr (RLDS) {
-      for (int i = threadIdx.x; i < N; i += B) L.X2[i] = sqrt(L.X2[i]) * (1.0 + 1e-12);
-      reach = L.X2;
+      if (DB) {
+        for (int i = threadIdx.x; i < N; i += B) L.X2[i] = sqrt(L.X2[i]) * (1.0 + 1e-12);
+        reach = (const double*)L.X2;
+      } else {
+        for (int i = threadIdx.x; i < N; i += B) ts.rglob[i] = sqrt(ts.rglob[i]) * (1.0 + 1e-12);
+        reach = ts.rglob;
+      }
     }
   }
   const double reach_all = 0.5 * (sqrt(rl2) - rcm);  // every atom's reach at radius sqrt(rl2)
@@ -1059,7 +1072,7 @@ __device__ __forceinline__ void tile_body(const PathArgs& a, int tile, const Til
         }
       }
     }
-    if constexpr (DB) {
+    if (DB) {
       lds_f64* t = L.X;
       L.X = L.X2;
       L.X2 = t;
@@ -1205,7 +1218,7 @@ __global__ void __launch_bounds__(1024) lj_em_kernel(PathArgs a, const double* x
   constexpr int XS = DB ? XS_R : 3;
   const TileScratch ts = block_scratch(sc);
   const int N = a.n_atoms;
-  TileLDS L = carve_lds(lds, N, a.nc * a.nc * a.nc, DB, false);
+  TileLDS L = carve_lds(lds, N, a.nc * a.nc * a.nc, DB, false, DB);
   const size_t slice = (size_t)3 * N;
   const double ib = a.lj.inv_box;
   const int B = blockDim.x;
@@ -1291,11 +1304,12 @@ __global__ void __launch_bounds__(1024) lj_em_kernel(PathArgs a, const double* x
 
 hipError_t launch_lj_em(const PathArgs& a, const double* xi, double amp, double* xout,
                         const BlockScratch& s, const FusedLaunch& L, hipStream_t st) {
-  const void* k = L.r_in_lds ? (const void*)lj_em_kernel<true> : (const void*)lj_em_kernel<false>;
+  const bool db = L.r_in_lds && L.lds2;  // else one array of positions (3 doubles per slot)
+  const void* k = db ? (const void*)lj_em_kernel<true> : (const void*)lj_em_kernel<false>;
   hipError_t e =
       hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.lds_bytes);
   if (e != hipSuccess) return e;
-  if (L.r_in_lds)
+  if (db)
     hipLaunchKernelGGL(lj_em_kernel<true>, dim3(1), dim3(L.block), L.lds_bytes, st, a, xi, amp,
                        xout, s);
   else
