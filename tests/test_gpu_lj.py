@@ -285,13 +285,14 @@ def test_lj4000_ragged_tiles_sampled(device):
     _check_sampled(w, X, S, s, g, [0, 1, 31, 32, 33, 64, 95, 96, 99, 100])
 
 
-def test_lj2048_one_slot_array_sampled(device):
+@pytest.mark.parametrize("nlist", ["full", "half"])
+def test_lj2048_one_slot_array_sampled(device, nlist):
     """2048 atoms: rho in LDS with one slot array (two do not fit), so the
     next slice loads after pass 2 and the per-atom list reaches wait in
     global scratch; 16-step tiles and a ragged last tile."""
     w = W.workload("lj864").with_atoms(2048).with_steps(70)
     X = W.tethered_path(w)
-    S, s, g = run(w, X, tuning=P.make_tuning("fused", tile=16))
+    S, s, g = run(w, X, tuning=P.make_tuning("fused", tile=16, neighbour_list=nlist))
     _check_sampled(w, X, S, s, g, [0, 1, 15, 16, 17, 47, 48, 63, 64, 69, 70])
 
 
