@@ -15,12 +15,15 @@ Modules
   philox     : Philox4x32-10 counter-based generator, uniforms, Box-Muller normals
   sampling   : random fragmentation, free-particle trial paths and the
                fragment-wise Metropolis-Hastings step (Sec. III)
+  pamd       : the sample-shift-regrow integration loop (Sec. II B, Figs. 1-2)
+  langevin   : a gradient-informed (Metropolis-adjusted Langevin) path move, an
+               extension targeting exp(-S) of Eq. 4
 
 Parity status: every function here is pinned by a test in tests/test_oracle_*.py
 against closed forms, invariants, finite or complex-step differences, brute
 force, or published known-answer values.
 """
-from . import potentials, forces, action, em, philox, sampling  # noqa: F401
+from . import potentials, forces, action, em, philox, sampling, pamd, langevin  # noqa: F401
 from .potentials import Harmonic, LennardJones  # noqa: F401
 from .action import (residuals, per_step_action, path_action, path_gradient,  # noqa: F401
                      log_norm, slice_terms)
