@@ -151,7 +151,8 @@ def _parser():
                     help="lj864 (default), lj108, lj27, ho1d, batch64, sweep4000, "
                          "em864 or em27 (sequential Euler-Maruyama integration), "
                          "pamd864 or pamd27 (the path-based integration loop), "
-                         "langevin864 (gradient-informed path move)")
+                         "langevin864 (gradient-informed path move), "
+                         "ho_table2 (the harmonic integration schedules: accuracy and rate)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--list", choices=["auto", "full", "half"], default="auto")
@@ -202,6 +203,8 @@ def main(argv=None) -> int:
         return bench_pamd(args, W.workload("lj" + args.workload[4:]))
     if args.workload == "langevin864":
         return bench_langevin(args, W.workload("lj864"))
+    if args.workload == "ho_table2":
+        return bench_ho_table2(args)
     w = W.workload(args.workload)
     if w.potential == "harmonic":
         return bench_harmonic(args, w)
@@ -865,6 +868,120 @@ def bench_langevin(args, w, tau: float = 1e-7) -> int:
               "acceptance": n_acc / args.steps, "parallelism": "single GPU"}
     _line(units / (ms * 1e-3), ms, args, "f64", config, roof, None,
           metric="langevin_move_slice_atoms_per_s", unit="slice_atoms/s")
+    return 0
+
+
+# The paper's harmonic-oscillator schedules (Sec. IV A, Table II): k = beta =
+# D = gamma = 1, PAMD at dt = 0.4, Euler at dt_E = 0.025.
+HO_SIMS = [
+    {"name": "Simulation 1", "n_path": 16, "n_sample": 2, "n_shift": 2, "l_min": 3, "l_max": 3,
+     "paper": {"chi": 16, "E_eq": 0.003, "E_dyn": 0.003}},
+    {"name": "Simulation 2", "n_path": 256, "n_sample": 1, "n_shift": 8, "l_min": 4, "l_max": 5,
+     "paper": {"chi": 128, "E_eq": 0.003, "E_dyn": 0.011}},
+    {"name": "Simulation 3", "n_path": 4096, "n_sample": 1, "n_shift": 64, "l_min": 4, "l_max": 8,
+     "paper": {"chi": 1024, "E_eq": 0.005, "E_dyn": 0.029}},
+]
+
+
+def _ho_errors(x: np.ndarray, dt: float) -> dict:
+    """E_eq (Eq. 12) and E_dyn (Eqs. 13-15) of harmonic trajectories sampled
+    every dt (x: time x independent trajectories).
+
+    E_eq: L2 distance between the sampled and the exact (unit normal) position
+    densities, both normalised; from a histogram (bins 0.25 wide on [-5, 5],
+    noisy at these trajectory lengths) and from the normal density with the
+    sampled variance.  E_dyn: |kappa - kappa_s| / k with kappa_s the slope of
+    the log autocovariance fitted on t in [0, 4]."""
+    grid = np.linspace(-12.0, 12.0, 24001)
+    dg = grid[1] - grid[0]
+    p = np.exp(-0.5 * grid ** 2) / math.sqrt(2 * math.pi)
+    var = float(np.mean(x * x))
+    q = np.exp(-0.5 * grid ** 2 / var) / math.sqrt(2 * math.pi * var)
+    e_fit = math.sqrt(float(np.sum((p - q) ** 2)) * dg)
+    edges = np.linspace(-5.0, 5.0, 41)
+    h, _ = np.histogram(x, bins=edges, density=True)
+    mid = 0.5 * (edges[1:] + edges[:-1])
+    ph = np.exp(-0.5 * mid ** 2) / math.sqrt(2 * math.pi)
+    e_hist = math.sqrt(float(np.sum((ph - h) ** 2)) * (edges[1] - edges[0]))
+    x = x.reshape(x.shape[0], -1)
+    lags = np.arange(0, int(round(4.0 / dt)) + 1)
+    c = np.array([np.mean(x[:x.shape[0] - k] * x[k:]) for k in lags])
+    slope = np.polyfit(lags * dt, np.log(c), 1)[0]
+    return {"E_eq_fit": e_fit, "E_eq_hist": e_hist, "E_dyn": abs(1.0 + slope), "variance": var}
+
+
+def bench_ho_table2(args, t_total: float = 100000.0, euler_dofs: int = 64) -> int:
+    """The three harmonic schedules of Table II run by the integration loop on
+    the GPU (one degree of freedom, x_0 drawn from the dt = 0.4 Euler chain's
+    stationary law), each over t_total time units, beside the GPU Euler
+    integrator at dt_E = 0.025 (euler_dofs independent oscillators over
+    t_total / 4 each); reports E_eq and E_dyn next to the paper's.  The JSON value is Simulation 1's
+    simulated time per wall-clock second."""
+    import torch
+    import paper_1907_09529_amd as P
+    P.load()
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    pot = P.make_potential("harmonic", k=1.0)
+    dt, dt_e = 0.4, 0.025
+    rng = np.random.default_rng(W.SEED_BASE + 40)
+    results, sim1_rate, sim1_ms = [], None, None
+    for sim in HO_SIMS:
+        n_path, n_shift = sim["n_path"], sim["n_shift"]
+        n_events = int(round(t_total / (dt * n_shift)))
+        X = np.zeros((n_path + 1, 1, 1))
+        X[0] = rng.standard_normal() * math.sqrt(1.25)
+        for n in range(n_path):
+            X[n + 1] = 0.6 * X[n] + math.sqrt(0.8) * rng.standard_normal()
+        path = P.make_path(n_path, 1, 1, dt, 1.0, 1.0)
+        x = torch.from_numpy(X).to(dev)
+        ex = torch.empty(n_path, dtype=torch.float64, device=dev)
+        P.pamd_excess_action(path, pot, x, ex)
+        counters = torch.zeros(2, dtype=torch.int64, device=dev)
+        traj = torch.empty((n_events * n_shift, 1, 1), dtype=torch.float64, device=dev)
+        ws = P.workspace(P.pamd_run_workspace_size(path, pot, n_shift))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        P.pamd_run(path, pot, 0x5EED + n_path, sim["l_min"], sim["l_max"], sim["n_sample"],
+                   n_shift, n_events, counters, x, torch.empty_like(x), torch.empty_like(x), ex,
+                   torch.empty_like(ex), traj, ws=ws)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        err = _ho_errors(traj.cpu().numpy().ravel()[n_path:], dt)
+        rate = n_events * n_shift * dt / wall
+        if sim1_rate is None:
+            sim1_rate, sim1_ms = rate, wall * 1e3 / n_events
+        results.append({"name": sim["name"], "events": n_events, "event_ms": wall * 1e3 / n_events,
+                        "md_time_per_s": rate, **{k: round(v, 4) for k, v in err.items()},
+                        "paper": sim["paper"]})
+    # Euler at dt_E: independent oscillators from the stationary law
+    n_e = int(round(t_total / 4 / dt_e))
+    path_e = P.make_path(n_e, euler_dofs, 1, dt_e, 1.0, 1.0)
+    xi = torch.randn((n_e, 1, euler_dofs), dtype=torch.float64, device=dev,
+                     generator=torch.Generator(device=dev).manual_seed(W.SEED_BASE + 41))
+    x0 = torch.from_numpy(rng.standard_normal((1, euler_dofs))).to(dev)
+    out = torch.empty((n_e + 1, 1, euler_dofs), dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    P.pamd_em_integrate(path_e, pot, x0, xi, out)
+    torch.cuda.synchronize()
+    wall_e = time.perf_counter() - t0
+    err_e = _ho_errors(out.cpu().numpy()[1:, 0, :], dt_e)
+    euler = {"dt_E": dt_e, "steps": n_e, "oscillators": euler_dofs,
+             "md_time_per_s": n_e * dt_e / wall_e,
+             **{k: round(v, 4) for k, v in err_e.items()},
+             "paper": {"E_eq": 0.003, "E_dyn": 0.010}}
+    roof = {"bound": "hbm", "achieved": None, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
+            "frac": None, "traffic": None,
+            "note": "launch-bound: one degree of freedom; the loop's kernels move bytes, not "
+                    "bandwidth"}
+    config = {"workload": f"harmonic oscillator integration, Table II schedules at dt {dt}, "
+                          f"{t_total:g} time units each, Euler at dt_E {dt_e}",
+              "simulations": results, "euler": euler,
+              "exact_euler_law_dt0.4": {"variance": 1.25, "E_eq": 0.0498, "E_dyn": 0.2771},
+              "parallelism": "single GPU"}
+    _line(sim1_rate, sim1_ms, args, "f64", config, roof, None, metric="md_time_per_wall_s",
+          unit="md_time/s")
     return 0
 
 
