@@ -149,6 +149,27 @@ typedef struct pamd_tuning {
 int pamd_workspace_size(const pamd_path* path, const pamd_potential* pot,
                         const pamd_tuning* tuning, size_t* bytes);
 
+/* The launch the library would use for this problem and tuning (host-only;
+ * no device is touched): the planner's choices, for callers that need to
+ * know the time tiling (tests of tile edges, work accounting).  Fields that
+ * do not apply are 0 (the harmonic kernel has no tiles, cells or lists). */
+typedef struct pamd_launch {
+  int32_t algo;             /* PAMD_ALGO_FUSED or PAMD_ALGO_PLAIN (Lennard-Jones), 0 (harmonic) */
+  int32_t block;            /* threads per workgroup */
+  int32_t tile;             /* time steps per workgroup tile (fused) */
+  int32_t n_tiles;          /* ceil(n_steps / tile) */
+  int32_t grid;             /* workgroups launched (tiles are taken in a grid-stride loop) */
+  int32_t cells;            /* cells per axis of the list build (0: all pairs) */
+  int32_t reach;            /* stencil half-width in cells */
+  int32_t max_neighbours;   /* list capacity per atom */
+  int32_t neighbour_list;   /* PAMD_LIST_FULL or PAMD_LIST_HALF */
+  int32_t lds_bytes;        /* shared memory per workgroup */
+  double skin;              /* list skin in length units */
+} pamd_launch;
+
+int pamd_launch_info(const pamd_path* path, const pamd_potential* pot, const pamd_tuning* tuning,
+                     pamd_launch* out);
+
 /* Action S[X] (Eq. 4 without normalisation).
  *   x         device, (N+1) * n_dim * n_atoms float64, layout above
  *   action    device, 1 float64 (written)
@@ -366,10 +387,13 @@ int pamd_em_integrate(const pamd_path* path, const pamd_potential* pot,
                       double* x_out, void* ws, size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------------------
- * Autotuning: times candidate (block, tile, skin) choices for this problem on
- * the given inputs and caches the fastest for later calls with the same
- * (potential kind, n_atoms, cells per axis, precision) key.  Synchronises the
- * stream.  `best` (host, may be NULL) receives the choice.
+ * Autotuning: times candidate (block, tile, skin, list kind) choices for this
+ * problem on the given inputs and caches the fastest for later calls whose
+ * key matches: potential kind, n_atoms, precision, floor(log2 n_steps), and
+ * for Lennard-Jones the box edge and cutoff.  Single-path calls and batch
+ * members made after it (pamd_batch_create) take their launch from the cache
+ * when no tuning field overrides it.  Synchronises the stream.  `best` (host,
+ * may be NULL) receives the choice.
  * ---------------------------------------------------------------------- */
 int pamd_autotune(const pamd_path* path, const pamd_potential* pot, const double* x,
                   double* grad_scratch, void* ws, size_t ws_bytes, void* stream,

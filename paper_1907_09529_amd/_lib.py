@@ -50,6 +50,13 @@ class PamdTuning(ctypes.Structure):
                 ("reserved0", c_int32)]
 
 
+class PamdLaunch(ctypes.Structure):
+    _fields_ = [("algo", c_int32), ("block", c_int32), ("tile", c_int32), ("n_tiles", c_int32),
+                ("grid", c_int32), ("cells", c_int32), ("reach", c_int32),
+                ("max_neighbours", c_int32), ("neighbour_list", c_int32), ("lds_bytes", c_int32),
+                ("skin", c_double)]
+
+
 class PamdError(RuntimeError):
     def __init__(self, code: int, func: str, msg: str):
         super().__init__(f"{func}: {ERROR_NAMES.get(code, code)}: {msg}")
@@ -63,6 +70,7 @@ _TUNE = POINTER(PamdTuning)
 
 _SIGNATURES = {
     "pamd_workspace_size": (c_int32, [_PATH, _POT, _TUNE, POINTER(c_size_t)]),
+    "pamd_launch_info": (c_int32, [_PATH, _POT, _TUNE, POINTER(PamdLaunch)]),
     "pamd_action": (c_int32, [_PATH, _POT, _TUNE, c_void_p, c_void_p, c_void_p, c_void_p,
                               c_size_t, c_void_p]),
     "pamd_action_grad": (c_int32, [_PATH, _POT, _TUNE, c_void_p, c_void_p, c_void_p, c_void_p,

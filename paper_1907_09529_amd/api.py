@@ -14,13 +14,13 @@ from typing import Optional, Sequence
 import torch
 
 from . import _lib
-from ._lib import (PamdPath, PamdPotential, PamdTuning, PamdError, PAMD_HARMONIC, PAMD_LJ,
+from ._lib import (PamdPath, PamdPotential, PamdTuning, PamdLaunch, PamdError, PAMD_HARMONIC, PAMD_LJ,
                    PAMD_FP64, PAMD_FP32_FORCE, PAMD_ALGO_AUTO, PAMD_ALGO_FUSED,
                    PAMD_ALGO_PLAIN)
 
 __all__ = [
-    "PamdPath", "PamdPotential", "PamdTuning", "PamdError", "make_path", "make_potential",
-    "make_tuning", "pamd_workspace_size", "pamd_action", "pamd_action_grad",
+    "PamdPath", "PamdPotential", "PamdTuning", "PamdLaunch", "PamdError", "make_path",
+    "make_potential", "make_tuning", "pamd_workspace_size", "pamd_launch_info", "pamd_action", "pamd_action_grad",
     "pamd_excess_action", "pamd_log_norm", "pamd_mh_workspace_size", "pamd_mh_step",
     "pamd_em_workspace_size", "pamd_em_integrate", "pamd_shift", "pamd_run_workspace_size",
     "pamd_run", "pamd_langevin_workspace_size", "pamd_langevin_step", "pamd_autotune", "PamdBatch", "PamdGraph", "workspace",
@@ -57,22 +57,72 @@ def _ref(s):
     return ctypes.byref(s) if s is not None else None
 
 
-def _ptr(t: Optional[torch.Tensor], dtype=torch.float64, name: str = "tensor"):
+class _Dev:
+    """A tensor argument whose size, type and layout have been checked; its
+    device is checked in _call, after every argument's size (so that a
+    wrongly sized buffer is reported as such wherever it stands)."""
+    __slots__ = ("t", "name")
+
+    def __init__(self, t, name):
+        self.t, self.name = t, name
+
+
+def _ptr(t: Optional[torch.Tensor], dtype=torch.float64, name: str = "tensor",
+         numel: Optional[int] = None):
+    """Checks what the C ABI cannot: element type, contiguity and size (the
+    library reads or writes exactly ``numel`` elements, so a smaller tensor is
+    refused); _call then checks the device (the current HIP device)."""
     if t is None:
         return None
-    if not t.is_cuda:
-        raise ValueError(f"{name} must be a device tensor")
     if dtype is not None and t.dtype != dtype:
         raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
     if not t.is_contiguous():
         raise ValueError(f"{name} must be contiguous")
-    return ctypes.c_void_p(t.data_ptr())
+    if numel is not None and t.numel() < numel:
+        raise ValueError(f"{name} has {t.numel()} elements, {numel} needed")
+    return _Dev(t, name)
 
 
-def _stream(stream) -> ctypes.c_void_p:
-    if stream is None:
-        stream = torch.cuda.current_stream()
-    return ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+def _call(fn: str, *args):
+    out = []
+    for a in args:
+        if isinstance(a, _Dev):
+            if not a.t.is_cuda:
+                raise ValueError(f"{a.name} must be a device tensor")
+            if a.t.device.index != torch.cuda.current_device():
+                raise ValueError(f"{a.name} is on {a.t.device}, not the current device "
+                                 f"cuda:{torch.cuda.current_device()}")
+            a = ctypes.c_void_p(a.t.data_ptr())
+        elif isinstance(a, _Stream):
+            a = a.handle()
+        out.append(a)
+    return _lib.call(fn, *out)
+
+
+def _path_elems(path: PamdPath) -> int:
+    """Elements of a path (or gradient) buffer: (N + 1) n_dim n_atoms."""
+    return (int(path.n_steps) + 1) * int(path.n_dim) * int(path.n_atoms)
+
+
+def _dof(path: PamdPath) -> int:
+    return int(path.n_dim) * int(path.n_atoms)
+
+
+class _Stream:
+    """The HIP stream argument, resolved in _call after the tensor checks
+    (None means torch's current stream)."""
+    __slots__ = ("s",)
+
+    def __init__(self, s):
+        self.s = s
+
+    def handle(self) -> ctypes.c_void_p:
+        s = torch.cuda.current_stream() if self.s is None else self.s
+        return ctypes.c_void_p(s.cuda_stream if hasattr(s, "cuda_stream") else int(s))
+
+
+def _stream(stream) -> _Stream:
+    return _Stream(stream)
 
 
 def workspace(nbytes: int, device=None) -> torch.Tensor:
@@ -87,9 +137,17 @@ def workspace(nbytes: int, device=None) -> torch.Tensor:
 def pamd_workspace_size(path: PamdPath, pot: PamdPotential,
                         tuning: Optional[PamdTuning] = None) -> int:
     n = ctypes.c_size_t(0)
-    _lib.call("pamd_workspace_size", ctypes.byref(path), ctypes.byref(pot), _ref(tuning),
+    _call("pamd_workspace_size", ctypes.byref(path), ctypes.byref(pot), _ref(tuning),
               ctypes.byref(n))
     return int(n.value)
+
+
+def pamd_launch_info(path: PamdPath, pot: PamdPotential,
+                     tuning: Optional[PamdTuning] = None) -> PamdLaunch:
+    out = PamdLaunch()
+    _call("pamd_launch_info", ctypes.byref(path), ctypes.byref(pot), _ref(tuning),
+          ctypes.byref(out))
+    return out
 
 
 def _ws(path, pot, tuning, ws, sizer=pamd_workspace_size):
@@ -100,26 +158,31 @@ def _ws(path, pot, tuning, ws, sizer=pamd_workspace_size):
 
 
 def pamd_action(path, pot, x, action, per_step=None, ws=None, tuning=None, stream=None):
+    args = (_ptr(x, name="x", numel=_path_elems(path)), _ptr(action, name="action", numel=1),
+            _ptr(per_step, name="per_step", numel=path.n_steps))
     ws, _ = _ws(path, pot, tuning, ws)
-    _lib.call("pamd_action", ctypes.byref(path), ctypes.byref(pot), _ref(tuning),
-              _ptr(x, name="x"), _ptr(action, name="action"), _ptr(per_step, name="per_step"),
+    _call("pamd_action", ctypes.byref(path), ctypes.byref(pot), _ref(tuning), *args,
               _ptr(ws, None, "ws"), ctypes.c_size_t(ws.numel()), _stream(stream))
 
 
 def pamd_action_grad(path, pot, x, grad, action=None, per_step=None, step_weights=None,
                      ws=None, tuning=None, stream=None):
+    args = (_ptr(x, name="x", numel=_path_elems(path)),
+            _ptr(step_weights, name="step_weights", numel=path.n_steps),
+            _ptr(action, name="action", numel=1),
+            _ptr(per_step, name="per_step", numel=path.n_steps),
+            _ptr(grad, name="grad", numel=_path_elems(path)))
     ws, _ = _ws(path, pot, tuning, ws)
-    _lib.call("pamd_action_grad", ctypes.byref(path), ctypes.byref(pot), _ref(tuning),
-              _ptr(x, name="x"), _ptr(step_weights, name="step_weights"),
-              _ptr(action, name="action"), _ptr(per_step, name="per_step"),
-              _ptr(grad, name="grad"), _ptr(ws, None, "ws"), ctypes.c_size_t(ws.numel()),
-              _stream(stream))
+    _call("pamd_action_grad", ctypes.byref(path), ctypes.byref(pot), _ref(tuning), *args,
+              _ptr(ws, None, "ws"), ctypes.c_size_t(ws.numel()), _stream(stream))
 
 
 def pamd_excess_action(path, pot, x, excess, per_step=None, ws=None, tuning=None, stream=None):
+    args = (_ptr(x, name="x", numel=_path_elems(path)),
+            _ptr(excess, name="excess", numel=path.n_steps),
+            _ptr(per_step, name="per_step", numel=path.n_steps))
     ws, _ = _ws(path, pot, tuning, ws)
-    _lib.call("pamd_excess_action", ctypes.byref(path), ctypes.byref(pot), _ref(tuning),
-              _ptr(x, name="x"), _ptr(excess, name="excess"), _ptr(per_step, name="per_step"),
+    _call("pamd_excess_action", ctypes.byref(path), ctypes.byref(pot), _ref(tuning), *args,
               _ptr(ws, None, "ws"), ctypes.c_size_t(ws.numel()), _stream(stream))
 
 
@@ -132,7 +195,7 @@ def pamd_log_norm(path: PamdPath) -> float:
 # ---------------------------------------------------------------------------
 def pamd_mh_workspace_size(path, pot, tuning=None) -> int:
     n = ctypes.c_size_t(0)
-    _lib.call("pamd_mh_workspace_size", ctypes.byref(path), ctypes.byref(pot), _ref(tuning),
+    _call("pamd_mh_workspace_size", ctypes.byref(path), ctypes.byref(pot), _ref(tuning),
               ctypes.byref(n))
     return int(n.value)
 
@@ -142,12 +205,15 @@ def pamd_mh_step(path, pot, seed: int, l_min: int, l_max: int, sweep_counter: to
                  frag_delta=None, frag_accept=None, step_info=None, ws=None, tuning=None,
                  stream=None):
     ws, _ = _ws(path, pot, tuning, ws, pamd_mh_workspace_size)
-    _lib.call("pamd_mh_step", ctypes.byref(path), ctypes.byref(pot), _ref(tuning),
+    _call("pamd_mh_step", ctypes.byref(path), ctypes.byref(pot), _ref(tuning),
               ctypes.c_uint64(seed), ctypes.c_int32(l_min), ctypes.c_int32(l_max),
-              _ptr(sweep_counter, torch.int64, "sweep_counter"), _ptr(x, name="x"),
-              _ptr(excess, name="excess"), _ptr(trial, name="trial"),
-              _ptr(frag_delta, name="frag_delta"), _ptr(frag_accept, torch.int32, "frag_accept"),
-              _ptr(step_info, torch.int32, "step_info"), _ptr(ws, None, "ws"),
+              _ptr(sweep_counter, torch.int64, "sweep_counter", 1),
+              _ptr(x, name="x", numel=_path_elems(path)),
+              _ptr(excess, name="excess", numel=path.n_steps),
+              _ptr(trial, name="trial", numel=_path_elems(path)),
+              _ptr(frag_delta, name="frag_delta", numel=path.n_steps + 2),
+              _ptr(frag_accept, torch.int32, "frag_accept", path.n_steps + 2),
+              _ptr(step_info, torch.int32, "step_info", 4), _ptr(ws, None, "ws"),
               ctypes.c_size_t(ws.numel()), _stream(stream))
 
 
@@ -156,16 +222,19 @@ def pamd_mh_step(path, pot, seed: int, l_min: int, l_max: int, sweep_counter: to
 # ---------------------------------------------------------------------------
 def pamd_shift(path, seed: int, n_shift: int, event_counter: torch.Tensor, x_in, x_out,
                excess_in=None, excess_out=None, traj_out=None, stream=None):
-    _lib.call("pamd_shift", ctypes.byref(path), ctypes.c_uint64(seed), ctypes.c_int32(n_shift),
-              _ptr(event_counter, torch.int64, "event_counter"), _ptr(x_in, name="x_in"),
-              _ptr(x_out, name="x_out"), _ptr(excess_in, name="excess_in"),
-              _ptr(excess_out, name="excess_out"), _ptr(traj_out, name="traj_out"),
+    _call("pamd_shift", ctypes.byref(path), ctypes.c_uint64(seed), ctypes.c_int32(n_shift),
+              _ptr(event_counter, torch.int64, "event_counter", 1),
+              _ptr(x_in, name="x_in", numel=_path_elems(path)),
+              _ptr(x_out, name="x_out", numel=_path_elems(path)),
+              _ptr(excess_in, name="excess_in", numel=path.n_steps),
+              _ptr(excess_out, name="excess_out", numel=path.n_steps),
+              _ptr(traj_out, name="traj_out", numel=int(n_shift) * _dof(path)),
               _stream(stream))
 
 
 def pamd_run_workspace_size(path, pot, n_shift: int, tuning=None) -> int:
     n = ctypes.c_size_t(0)
-    _lib.call("pamd_run_workspace_size", ctypes.byref(path), ctypes.byref(pot), _ref(tuning),
+    _call("pamd_run_workspace_size", ctypes.byref(path), ctypes.byref(pot), _ref(tuning),
               ctypes.c_int32(n_shift), ctypes.byref(n))
     return int(n.value)
 
@@ -175,13 +244,17 @@ def pamd_run(path, pot, seed: int, l_min: int, l_max: int, n_sample: int, n_shif
              traj_out=None, level_stats=None, ws=None, tuning=None, stream=None):
     if ws is None:
         ws = workspace(pamd_run_workspace_size(path, pot, n_shift, tuning))
-    _lib.call("pamd_run", ctypes.byref(path), ctypes.byref(pot), _ref(tuning),
+    _call("pamd_run", ctypes.byref(path), ctypes.byref(pot), _ref(tuning),
               ctypes.c_uint64(seed), ctypes.c_int32(l_min), ctypes.c_int32(l_max),
               ctypes.c_int32(n_sample), ctypes.c_int32(n_shift), ctypes.c_int32(n_events),
-              _ptr(counters, torch.int64, "counters"), _ptr(x, name="x"),
-              _ptr(x_alt, name="x_alt"), _ptr(trial, name="trial"), _ptr(excess, name="excess"),
-              _ptr(excess_alt, name="excess_alt"), _ptr(traj_out, name="traj_out"),
-              _ptr(level_stats, torch.int64, "level_stats"), _ptr(ws, None, "ws"),
+              _ptr(counters, torch.int64, "counters", 2),
+              _ptr(x, name="x", numel=_path_elems(path)),
+              _ptr(x_alt, name="x_alt", numel=_path_elems(path)),
+              _ptr(trial, name="trial", numel=_path_elems(path)),
+              _ptr(excess, name="excess", numel=path.n_steps),
+              _ptr(excess_alt, name="excess_alt", numel=path.n_steps),
+              _ptr(traj_out, name="traj_out", numel=int(n_events) * int(n_shift) * _dof(path)),
+              _ptr(level_stats, torch.int64, "level_stats", 62), _ptr(ws, None, "ws"),
               ctypes.c_size_t(ws.numel()), _stream(stream))
 
 
@@ -190,7 +263,7 @@ def pamd_run(path, pot, seed: int, l_min: int, l_max: int, n_sample: int, n_shif
 # ---------------------------------------------------------------------------
 def pamd_langevin_workspace_size(path, pot, tuning=None) -> int:
     n = ctypes.c_size_t(0)
-    _lib.call("pamd_langevin_workspace_size", ctypes.byref(path), ctypes.byref(pot),
+    _call("pamd_langevin_workspace_size", ctypes.byref(path), ctypes.byref(pot),
               _ref(tuning), ctypes.byref(n))
     return int(n.value)
 
@@ -199,12 +272,15 @@ def pamd_langevin_step(path, pot, seed: int, tau: float, move_counter: torch.Ten
                        action, y, grad_y, accepted=None, log_alpha=None, ws=None, tuning=None,
                        stream=None):
     ws, _ = _ws(path, pot, tuning, ws, pamd_langevin_workspace_size)
-    _lib.call("pamd_langevin_step", ctypes.byref(path), ctypes.byref(pot), _ref(tuning),
+    _call("pamd_langevin_step", ctypes.byref(path), ctypes.byref(pot), _ref(tuning),
               ctypes.c_uint64(seed), ctypes.c_double(tau),
-              _ptr(move_counter, torch.int64, "move_counter"), _ptr(x, name="x"),
-              _ptr(grad, name="grad"), _ptr(action, name="action"), _ptr(y, name="y"),
-              _ptr(grad_y, name="grad_y"), _ptr(accepted, torch.int32, "accepted"),
-              _ptr(log_alpha, name="log_alpha"), _ptr(ws, None, "ws"),
+              _ptr(move_counter, torch.int64, "move_counter", 1),
+              _ptr(x, name="x", numel=_path_elems(path)),
+              _ptr(grad, name="grad", numel=_path_elems(path)),
+              _ptr(action, name="action", numel=1), _ptr(y, name="y", numel=_path_elems(path)),
+              _ptr(grad_y, name="grad_y", numel=_path_elems(path)),
+              _ptr(accepted, torch.int32, "accepted", 1),
+              _ptr(log_alpha, name="log_alpha", numel=1), _ptr(ws, None, "ws"),
               ctypes.c_size_t(ws.numel()), _stream(stream))
 
 
@@ -213,22 +289,26 @@ def pamd_langevin_step(path, pot, seed: int, tau: float, move_counter: torch.Ten
 # ---------------------------------------------------------------------------
 def pamd_em_workspace_size(path, pot, tuning=None) -> int:
     n = ctypes.c_size_t(0)
-    _lib.call("pamd_em_workspace_size", ctypes.byref(path), ctypes.byref(pot), _ref(tuning),
+    _call("pamd_em_workspace_size", ctypes.byref(path), ctypes.byref(pot), _ref(tuning),
               ctypes.byref(n))
     return int(n.value)
 
 
 def pamd_em_integrate(path, pot, x0, noise, x_out, ws=None, tuning=None, stream=None):
     ws, _ = _ws(path, pot, tuning, ws, pamd_em_workspace_size)
-    _lib.call("pamd_em_integrate", ctypes.byref(path), ctypes.byref(pot), _ref(tuning),
-              _ptr(x0, name="x0"), _ptr(noise, name="noise"), _ptr(x_out, name="x_out"),
+    _call("pamd_em_integrate", ctypes.byref(path), ctypes.byref(pot), _ref(tuning),
+              _ptr(x0, name="x0", numel=_dof(path)),
+              _ptr(noise, name="noise", numel=int(path.n_steps) * _dof(path)),
+              _ptr(x_out, name="x_out", numel=_path_elems(path)),
               _ptr(ws, None, "ws"), ctypes.c_size_t(ws.numel()), _stream(stream))
 
 
 def pamd_autotune(path, pot, x, grad_scratch, ws, stream=None) -> PamdTuning:
     best = PamdTuning()
-    _lib.call("pamd_autotune", ctypes.byref(path), ctypes.byref(pot), _ptr(x, name="x"),
-              _ptr(grad_scratch, name="grad_scratch"), _ptr(ws, None, "ws"),
+    _call("pamd_autotune", ctypes.byref(path), ctypes.byref(pot),
+              _ptr(x, name="x", numel=_path_elems(path)),
+              _ptr(grad_scratch, name="grad_scratch", numel=_path_elems(path)),
+              _ptr(ws, None, "ws"),
               ctypes.c_size_t(ws.numel()), _stream(stream), ctypes.byref(best))
     return best
 
@@ -246,13 +326,13 @@ class PamdBatch:
         self._paths = (PamdPath * n)(*paths)
         self._pots = (PamdPotential * n)(*pots)
         handle = ctypes.c_void_p()
-        _lib.call("pamd_batch_create", ctypes.c_int32(n), self._paths, self._pots, _ref(tuning),
+        _call("pamd_batch_create", ctypes.c_int32(n), self._paths, self._pots, _ref(tuning),
                   ctypes.byref(handle))
         self._h = handle
         xo = (ctypes.c_int64 * (n + 1))()
         so = (ctypes.c_int64 * (n + 1))()
         nb = ctypes.c_size_t(0)
-        _lib.call("pamd_batch_layout", self._h, xo, so, ctypes.byref(nb))
+        _call("pamd_batch_layout", self._h, xo, so, ctypes.byref(nb))
         self.x_offsets = list(xo)
         self.step_offsets = list(so)
         self.ws_bytes = int(nb.value)
@@ -261,7 +341,7 @@ class PamdBatch:
     def prepare(self, ws: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
         if ws is None:
             ws = workspace(self.ws_bytes)
-        _lib.call("pamd_batch_prepare", self._h, _ptr(ws, None, "ws"), ctypes.c_size_t(ws.numel()),
+        _call("pamd_batch_prepare", self._h, _ptr(ws, None, "ws"), ctypes.c_size_t(ws.numel()),
                   _stream(stream))
         self.ws = ws
         return ws
@@ -270,9 +350,12 @@ class PamdBatch:
                                weights_all=None, stream=None):
         if self.ws is None:
             self.prepare(stream=stream)
-        _lib.call("pamd_batch_action_grad", self._h, _ptr(x_all, name="x_all"),
-                  _ptr(weights_all, name="weights_all"), _ptr(actions, name="actions"),
-                  _ptr(per_step_all, name="per_step_all"), _ptr(grad_all, name="grad_all"),
+        nx, ns = self.x_offsets[-1], self.step_offsets[-1]
+        _call("pamd_batch_action_grad", self._h, _ptr(x_all, name="x_all", numel=nx),
+                  _ptr(weights_all, name="weights_all", numel=ns),
+                  _ptr(actions, name="actions", numel=self.n_paths),
+                  _ptr(per_step_all, name="per_step_all", numel=ns),
+                  _ptr(grad_all, name="grad_all", numel=nx),
                   _ptr(self.ws, None, "ws"), ctypes.c_size_t(self.ws.numel()), _stream(stream))
 
     def view(self, packed: torch.Tensor, p: int) -> torch.Tensor:
@@ -305,13 +388,13 @@ class PamdGraph:
         self._h = ctypes.c_void_p()
 
     def begin(self, stream):
-        _lib.call("pamd_graph_begin", _stream(stream))
+        _call("pamd_graph_begin", _stream(stream))
 
     def end(self, stream):
-        _lib.call("pamd_graph_end", _stream(stream), ctypes.byref(self._h))
+        _call("pamd_graph_end", _stream(stream), ctypes.byref(self._h))
 
     def launch(self, stream):
-        _lib.call("pamd_graph_launch", self._h, _stream(stream))
+        _call("pamd_graph_launch", self._h, _stream(stream))
 
     def close(self):
         if self._h.value:

@@ -500,6 +500,38 @@ int pamd_workspace_size(const pamd_path* p, const pamd_potential* v, const pamd_
   return PAMD_OK;
 }
 
+int pamd_launch_info(const pamd_path* p, const pamd_potential* v, const pamd_tuning* t,
+                     pamd_launch* out) {
+  if (!out) return fail(PAMD_EINVAL, "out is NULL");
+  Plan P;
+  int rc = make_plan(p, v, t, false, P);
+  if (rc) return rc;
+  std::memset(out, 0, sizeof(*out));
+  if (P.kind == PAMD_HARMONIC) return PAMD_OK;
+  out->algo = P.algo;
+  out->skin = P.skin;
+  if (P.algo == PAMD_ALGO_PLAIN) {
+    out->block = P.block;
+    out->cells = P.pcells.nc;
+    out->reach = P.pcells.reach;
+    out->max_neighbours = P.pkmax;
+    out->lds_bytes = (int32_t)P.plds;
+    out->tile = 1;
+    out->n_tiles = (int32_t)std::min<int64_t>(P.steps, INT32_MAX);
+    return PAMD_OK;
+  }
+  out->block = P.block;
+  out->tile = P.tile;
+  out->n_tiles = P.n_tiles;
+  out->grid = P.grid;
+  out->cells = P.cells.nc;
+  out->reach = P.cells.reach;
+  out->max_neighbours = P.kmax;
+  out->neighbour_list = P.half ? PAMD_LIST_HALF : PAMD_LIST_FULL;
+  out->lds_bytes = (int32_t)P.lds;
+  return PAMD_OK;
+}
+
 int pamd_action(const pamd_path* p, const pamd_potential* v, const pamd_tuning* t,
                 const double* x, double* action, double* per_step, void* ws, size_t ws_bytes,
                 void* stream) {

@@ -197,9 +197,12 @@ def lj864_full():
 
 
 def _sample_slices(w, tile):
+    """Slices on both sides of the first two tile edges and of the last one,
+    the path's ends, and six random slices."""
     rng = np.random.default_rng(w.seed + 11)
-    picks = {0, 1, w.n_steps - 1, w.n_steps, tile - 1, tile, tile + 1, 2 * tile,
-             w.n_steps - tile, w.n_steps - tile + 1}
+    last_edge = (w.n_steps - 1) // tile * tile
+    picks = {0, 1, w.n_steps - 1, w.n_steps, tile - 1, tile, tile + 1, 2 * tile - 1, 2 * tile,
+             2 * tile + 1, last_edge - 1, last_edge, last_edge + 1}
     picks |= set(int(v) for v in rng.integers(0, w.n_steps + 1, size=6))
     return sorted(p for p in picks if 0 <= p <= w.n_steps)
 
@@ -210,8 +213,12 @@ def test_lj864_full_size_sampled(device, lj864_full):
     assert np.all(s > 0) and np.all(np.isfinite(g))
     assert rel(S, math.fsum(s.tolist())) <= 1e-13
     pot = oracle_pot(w)
-    tile = max(1, min(32, w.n_steps // 512))
-    for m in _sample_slices(w, tile):
+    path, lpot = lib_descriptors(w)
+    tile = P.pamd_launch_info(path, lpot).tile   # the launch run() used (default tuning)
+    assert 1 <= tile < w.n_steps
+    picks = _sample_slices(w, tile)
+    print(f"lj864 full size: tile {tile}, sampled slices {picks}")
+    for m in picks:
         sm, gm = OA.slice_terms(X, m, pot, w.dt, w.D, w.gamma)
         assert rel_inf(g[m], gm) <= GRAD_TOL, m
         if sm is not None:
