@@ -2,15 +2,18 @@
 
 Workload (default): Lennard-Jones path, 864 atoms at reduced density 0.8442,
 T = 1, r_c = 2.5 sigma, cubic periodic box, dt = 1e-4, D = gamma = 1, 4096
-time steps; seeded synthetic path (FCC lattice plus a tethered Gaussian random
-walk with the free-diffusion step size, plus N(0, 0.01^2) per-slice noise),
-resident in device memory before timing.  One benchmark step = one
-pamd_action_grad call (FP64): action, per-step terms and the gradient of
-every slice.
+time steps.  The input is a seeded Euler-Maruyama path (Eq. 2) integrated on
+the GPU from the FCC lattice with the workload's own normal draws, slices
+1..N then perturbed by N(0, 0.01^2); it is resident in device memory before
+timing (``--input tethered`` selects the force-free stand-in instead).  One
+benchmark step = one pamd_action_grad call (FP64): action, per-step terms and
+the gradient of every slice.
 
 Prints one JSON line with the metric, the roofline of the dominant kernel
-(measured with HIP events around that kernel inside the timed region) and a
-CPU baseline (the oracle, timed on a bounded sample on this host's cores).
+(measured with HIP events around that kernel inside the timed region), the
+unfused (plain) form timed on the same input, and a CPU baseline: the oracle,
+timed on a bounded sample of the same path on this host's cores, in a child
+process that never touches the GPU.
 """
 from __future__ import annotations
 
@@ -32,14 +35,23 @@ if ROOT not in sys.path:
 import workloads as W  # noqa: E402
 
 PEAK_FP64_VALU = 78.6e12   # 256 CUs x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz
-PEAK_FP32_VALU = 157.3e12  # the FP32 vector rate (pair functions of the FP32-force variant)
 PEAK_HBM = 8.0e12
 
-# Algorithmic work per unique in-cutoff pair and per slice-atom (FMA = 2 flops,
-# rsqrt = 1 flop, rounding to integer not counted); derivation in the design doc.
-FLOP_FORCE_PAIR = 41
-FLOP_HV_PAIR = 59
-FLOP_SLICE_ATOM = 39
+# Algorithmic work, fixed before any kernel tuning (FMA = 2 flops, rsqrt = 1):
+# per unique in-cutoff pair, the force (difference, minimum image, r^2, the
+# pair scalar of Eq. 16, both atoms' sums) and the Hessian-vector product
+# (the scalars U'/r and (U'' - U'/r)/r^2, K w for w = rho_i - rho_j, both
+# atoms' sums); per slice-atom the residual, |r|^2 and the gradient row.
+# The roofline fraction uses these.
+FLOP_FORCE_PAIR = 34
+FLOP_HV_PAIR = 56
+FLOP_SLICE_ATOM = 25
+# A recount of every operation the fused kernel's source performs per unique
+# pair (the Hessian-vector pass recomputes the geometry: 29 of its 59), reported
+# beside the fraction, never in it.
+RECOUNT_FORCE_PAIR = 41
+RECOUNT_HV_PAIR = 59
+RECOUNT_SLICE_ATOM = 39
 BYTES_SLICE_ATOM = 48       # read x_n (24 B) + write g_n (24 B)
 
 # HBM bytes per launch of lj_fused_kernel on the default workload and tuning,
@@ -47,7 +59,15 @@ BYTES_SLICE_ATOM = 48       # read x_n (24 B) + write g_n (24 B)
 # (profiles/lj_fused_lj864x4096.md).  Reported only while the kernel sources
 # still hash to `sha`; any change to them makes `traffic` null until the
 # counters are taken again.
-MEASURED_TRAFFIC = {"sha": "ddefa2c5d4f307fc", "read_bytes": 1.5197e9, "write_bytes": 8.5405e8}
+MEASURED_TRAFFIC = {"sha": "ddefa2c5d4f307fc", "input": "tethered", "read_bytes": 1.5197e9,
+                    "write_bytes": 8.5405e8}
+# VALU instruction counters of the same kernel, input and tuning (per launch;
+# rocprofv3 --pmc, wave-level counts): the FP64 operations it issued, to set
+# beside the algorithmic fraction (they include candidates beyond the cutoff
+# and each pair's second evaluation from the partner's list).
+MEASURED_VALU = {"sha": "ddefa2c5d4f307fc", "input": "tethered", "valu": 4.5040e8,
+                 "fma_f64": 1.0297e8, "mul_f64": 8.0166e7, "add_f64": 7.6232e7,
+                 "trans_f64": 7.9844e6}
 TRAFFIC_SOURCES = ["paper_1907_09529_amd/csrc/lj_fused.hip", "paper_1907_09529_amd/csrc/device.hpp",
                    "paper_1907_09529_amd/csrc/internal.hpp"]
 
@@ -94,6 +114,71 @@ class HipEvents:
     def close(self):
         self.hip.hipEventDestroy(self.a)
         self.hip.hipEventDestroy(self.b)
+
+
+def em_path_device(w, P, torch, dev):
+    """Seeded Euler-Maruyama path of workload w (Eq. 2): the GPU integrator
+    steps the lattice with the workload's normal draws xi, then slices 1..N get
+    the workload's perturbation eta.  Same draws as the oracle-built test
+    inputs; the integrator is deterministic, so the path is too."""
+    x0 = W.initial_lattice(w.n_atoms, w.box)
+    xi, eta = W.draw_noise(w)
+    path = P.make_path(w.n_steps, w.n_atoms, 3, w.dt, w.D, w.gamma, "fp64")
+    pot = P.make_potential("lj", eps=w.eps, sigma=w.sigma, rc=w.cutoff, box=w.box)
+    x = torch.empty((w.n_steps + 1, 3, w.n_atoms), dtype=torch.float64, device=dev)
+    P.pamd_em_integrate(path, pot, torch.from_numpy(x0).to(dev), torch.from_numpy(xi).to(dev), x)
+    del xi
+    x[1:].add_(torch.from_numpy(eta).to(dev), alpha=w.perturb_sd)
+    torch.cuda.synchronize()
+    return x
+
+
+def input_path(args, w, P, torch, dev):
+    """The benchmark input on the device, and a name for it."""
+    if getattr(args, "input", "em") == "tethered":
+        return (torch.from_numpy(W.tethered_path(w)).to(dev),
+                "force-free tethered stand-in around the FCC lattice")
+    t0 = time.perf_counter()
+    x = em_path_device(w, P, torch, dev)
+    print(f"[bench] EM input path on the GPU: {time.perf_counter() - t0:.1f} s", file=sys.stderr,
+          flush=True)
+    return x, (f"seeded Euler-Maruyama path (Eq. 2) from the FCC lattice, seed {w.seed}, "
+               f"+ N(0, {w.perturb_sd:g}^2)")
+
+
+def cpu_baseline_child(X: np.ndarray, target_s: float = 12.0, method: str = "brute",
+                       workload: str = "lj864", member: int = -1) -> dict:
+    """Runs cpu_baseline on the host array X in a child Python process that
+    never initialises the GPU, so its worker pool can fork safely."""
+    import subprocess
+    import tempfile
+    fd, fn = tempfile.mkstemp(suffix=".npy", dir="/tmp")
+    os.close(fd)
+    try:
+        np.save(fn, np.ascontiguousarray(X))
+        cmd = [sys.executable, os.path.abspath(__file__), "--oracle-baseline", fn,
+               "--workload", workload, "--baseline-member", str(member),
+               "--baseline-target", str(target_s), "--baseline-method", method]
+        print(f"[bench] timing the CPU oracle baseline ({X.shape[0] - 1} steps available)",
+              file=sys.stderr, flush=True)
+        res = subprocess.run(cmd, capture_output=True, text=True, timeout=600)
+        if res.returncode != 0:
+            raise RuntimeError(f"oracle baseline failed: {res.stderr[-2000:]}")
+        return json.loads(res.stdout.strip().splitlines()[-1])
+    finally:
+        os.remove(fn)
+
+
+def oracle_baseline_main(args) -> int:
+    """Child-process side of cpu_baseline_child (no GPU)."""
+    X = np.load(args.oracle_baseline, mmap_mode="r")
+    if args.baseline_member >= 0:
+        w = W.batch_members()[args.baseline_member]
+    else:
+        w = W.workload(args.workload)
+    print(json.dumps(cpu_baseline(np.asarray(X), w, args.baseline_target, args.baseline_method)),
+          flush=True)
+    return 0
 
 
 def cpu_baseline(X: np.ndarray, w, target_s: float = 12.0, method: str = "brute") -> dict:
@@ -161,11 +246,20 @@ def _parser():
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="after timing, run one device copy of this many MiB (for counter calibration)")
+    ap.add_argument("--input", choices=["em", "tethered"], default="em",
+                    help="LJ input path: seeded Euler-Maruyama run (default) or the tethered stand-in")
+    ap.add_argument("--no-plain", action="store_true",
+                    help="skip timing the unfused form beside the fused one")
+    # internal: the CPU baseline's child process
+    ap.add_argument("--oracle-baseline", default="", help=argparse.SUPPRESS)
+    ap.add_argument("--baseline-member", type=int, default=-1, help=argparse.SUPPRESS)
+    ap.add_argument("--baseline-target", type=float, default=12.0, help=argparse.SUPPRESS)
+    ap.add_argument("--baseline-method", default="brute", help=argparse.SUPPRESS)
     return ap
 
 
 def _line(metric_value, ms, args, dtype, config, roof, baseline,
-          metric="slice_atom_action_grad_evals_per_s", unit="slice_atom_evals/s"):
+          metric="slice_atom_action_grad_evals_per_s", unit="slice_atom_evals/s", extra=None):
     out = {
         "metric": metric,
         "value": metric_value,
@@ -184,14 +278,18 @@ def _line(metric_value, ms, args, dtype, config, roof, baseline,
     }
     if baseline is not None:
         out["cpu_baseline"] = baseline
+    if extra:
+        out.update(extra)
     print(json.dumps(out), flush=True)
 
 
 def main(argv=None) -> int:
     args = _parser().parse_args(argv)
+    if args.oracle_baseline:
+        return oracle_baseline_main(args)
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the time-sharded "
-              "multi-GPU design is described in DESIGN.md and not built.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); sharding the "
+              "path along time across GPUs is a design that is not built.", file=sys.stderr)
         return 2
     if args.workload == "batch64":
         return bench_batch(args)
@@ -211,23 +309,37 @@ def main(argv=None) -> int:
     return bench_path(args, w)
 
 
+def _time_calls(step, n_warm, n_timed, lib, torch):
+    """Runs step() n_warm + n_timed times; returns (wall ms per call, the main
+    kernel's HIP-event ms per call) over the timed calls."""
+    for _ in range(n_warm):
+        step()
+    torch.cuda.synchronize()
+    events = [HipEvents() for _ in range(n_timed)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(n_timed):
+        lib.pamd_profile_events(events[k].a, events[k].b)
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kernel_ms = [e.elapsed_ms() for e in events]
+    for e in events:
+        e.close()
+    return (t1 - t0) * 1e3 / n_timed, float(np.mean(kernel_ms))
+
+
 def bench_path(args, w) -> int:
     """One Lennard-Jones path: one step = one pamd_action_grad call."""
-    print(f"[bench] generating {w.name}: {w.n_steps} steps x {w.n_atoms} atoms", file=sys.stderr,
-          flush=True)
-    X = W.tethered_path(w)
-    baseline = None
-    if not args.no_cpu_baseline:
-        # before any GPU initialisation: the worker processes are forked from here
-        print("[bench] timing the CPU oracle baseline", file=sys.stderr, flush=True)
-        baseline = cpu_baseline(X, w)
-
     import torch
     import paper_1907_09529_amd as P
 
-    P.load()
+    lib = P.load()
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    print(f"[bench] input {w.name}: {w.n_steps} steps x {w.n_atoms} atoms ({args.input})",
+          file=sys.stderr, flush=True)
+    x, input_name = input_path(args, w, P, torch, dev)
     precision = "fp32_force" if args.variant == "fp32_force" else "fp64"
     path = P.make_path(w.n_steps, w.n_atoms, 3, w.dt, w.D, w.gamma, precision)
     pot = P.make_potential("lj", eps=w.eps, sigma=w.sigma, rc=w.cutoff, box=w.box)
@@ -238,7 +350,6 @@ def bench_path(args, w) -> int:
                                neighbour_list=args.list)
     else:
         tuning = None
-    x = torch.from_numpy(X).to(dev)
     grad = torch.empty_like(x)
     act = torch.empty(1, dtype=torch.float64, device=dev)
     per_step = torch.empty(w.n_steps, dtype=torch.float64, device=dev)
@@ -250,6 +361,7 @@ def bench_path(args, w) -> int:
         print(f"[bench] autotuned: block {best.block} tile {best.tile} skin {best.skin}",
               file=sys.stderr, flush=True)
         ws = P.workspace(P.pamd_workspace_size(path, pot, tuning))
+    launch = P.pamd_launch_info(path, pot, tuning)
     stream = torch.cuda.current_stream()
 
     def step():
@@ -257,56 +369,80 @@ def bench_path(args, w) -> int:
                            tuning=tuning, stream=stream)
 
     print(f"[bench] warmup {args.warmup} steps, variant {args.variant}", file=sys.stderr, flush=True)
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    events = [HipEvents() for _ in range(args.steps)]
-    lib = P.load()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        lib.pamd_profile_events(events[k].a, events[k].b)
-        step()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    kernel_ms = [e.elapsed_ms() for e in events]
+    ms_per_step, k_ms = _time_calls(step, args.warmup, args.steps, lib, torch)
     if args.copy_probe_mb:
         n = args.copy_probe_mb * (1 << 20) // 8
         src = torch.ones(n, dtype=torch.float64, device=dev)
         dst = torch.empty_like(src)
         dst.copy_(src)
         torch.cuda.synchronize()
-    for e in events:
-        e.close()
-    ms_per_step = (t1 - t0) * 1e3 / args.steps
+        del src, dst
     units = w.n_steps * w.n_atoms
     value = units / (ms_per_step * 1e-3)
-    k_ms = float(np.mean(kernel_ms))
-    ppa = pairs_per_atom(X, w.box, w.cutoff)
+    idx = np.linspace(0, w.n_steps, 8).astype(int)
+    ppa = pairs_per_atom(x[torch.from_numpy(idx).to(dev)].cpu().numpy(), w.box, w.cutoff)
     flop_unit = ppa * (FLOP_FORCE_PAIR + FLOP_HV_PAIR) + FLOP_SLICE_ATOM
+    recount_unit = ppa * (RECOUNT_FORCE_PAIR + RECOUNT_HV_PAIR) + RECOUNT_SLICE_ATOM
     achieved = flop_unit * units / (k_ms * 1e-3)
-    traffic = None
     default_run = (args.variant == "fused" and args.workload == "lj864" and tuning is None
                    and not args.autotune)
-    if default_run and MEASURED_TRAFFIC["sha"] and MEASURED_TRAFFIC["sha"] == kernel_sources_sha():
+    sha = kernel_sources_sha()
+    traffic = None
+    if (default_run and MEASURED_TRAFFIC["sha"] == sha
+            and MEASURED_TRAFFIC.get("input", "tethered") == args.input):
         traffic = MEASURED_TRAFFIC["read_bytes"] + MEASURED_TRAFFIC["write_bytes"]
     roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64_VALU / 1e12,
             "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VALU, "traffic": traffic,
             "traffic_unit": "bytes per launch (HBM read + write)",
             "kernel": "lj_fused_kernel" if args.variant != "plain" else "plain pipeline",
-            "kernel_ms": k_ms, "flop_per_slice_atom": flop_unit, "pairs_per_atom": ppa,
+            "kernel_ms": k_ms, "flop_per_slice_atom": flop_unit,
+            "flop_constants": [FLOP_FORCE_PAIR, FLOP_HV_PAIR, FLOP_SLICE_ATOM],
+            "pairs_per_atom": ppa,
+            "frac_recount": recount_unit * units / (k_ms * 1e-3) / PEAK_FP64_VALU,
             "hbm_algorithmic_GBps": BYTES_SLICE_ATOM * units / (k_ms * 1e-3) / 1e9}
+    if default_run and MEASURED_VALU["sha"] == sha and MEASURED_VALU["input"] == args.input:
+        # FP64 operations the kernel issued (wave-level counts x 64 lanes), per
+        # second of the live kernel time, against the FP64 vector peak
+        ops = 64 * (2 * MEASURED_VALU["fma_f64"] + MEASURED_VALU["mul_f64"]
+                    + MEASURED_VALU["add_f64"] + MEASURED_VALU["trans_f64"])
+        roof["counter_fp64_frac"] = ops / (k_ms * 1e-3) / PEAK_FP64_VALU
+        roof["counter_valu_insts"] = MEASURED_VALU["valu"]
     if args.variant == "fp32_force":
-        # the pair functions run at the FP32 rate, the rest at the FP64 rate: the
-        # fraction against each peak bounds the kernel's use from both sides
-        roof["frac_vs_fp32_peak"] = achieved / PEAK_FP32_VALU
+        roof["note"] = ("float32 pair arithmetic: without packed float32 instructions (not "
+                        "used by this build) the vector float32 rate equals the float64 rate, "
+                        "so the same peak applies")
+    plain = None
+    if default_run and not args.no_plain:
+        # the unfused form on the same input, and its agreement with the fused one
+        tplain = P.make_tuning("plain")
+        wsp = P.workspace(P.pamd_workspace_size(path, pot, tplain))
+        gp = torch.empty_like(x)
+        actp = torch.empty(1, dtype=torch.float64, device=dev)
+
+        def step_plain():
+            P.pamd_action_grad(path, pot, x, gp, action=actp, ws=wsp, tuning=tplain, stream=stream)
+
+        n_plain = max(1, min(args.steps, 5))
+        print(f"[bench] plain form: {n_plain} timed calls", file=sys.stderr, flush=True)
+        p_ms, p_kms = _time_calls(step_plain, 1, n_plain, lib, torch)
+        step()
+        torch.cuda.synchronize()
+        plain = {"ms_per_call": p_ms, "fused_over_plain": p_ms / ms_per_step,
+                 "action_rel_diff": abs(float(actp.item()) - float(act.item())) / abs(float(act.item())),
+                 "grad_rel_diff": float((gp - grad).abs().max() / grad.abs().max())}
+        del wsp, gp
     config = {"workload": f"LJ {w.n_atoms} atoms x {w.n_steps} steps, rho {w.density}, T 1, "
-                          f"rc {w.cutoff:.4g}, dt {w.dt:g}, {args.variant}",
-              "neighbour_list": args.list,
+                          f"rc {w.cutoff:.4g}, dt {w.dt:g}, {args.variant}; input: {input_name}",
+              "neighbour_list": args.list, "input": args.input,
               "n_atoms": w.n_atoms, "n_steps": w.n_steps, "variant": args.variant,
-              "parallelism": "single GPU"}
+              "tile": launch.tile, "block": launch.block, "parallelism": "single GPU"}
+    baseline = None
+    if not args.no_cpu_baseline:
+        host = x[:min(w.n_steps + 1, 4097)].cpu().numpy()
+        baseline = cpu_baseline_child(host, workload=args.workload)
+    extra = {"plain": plain} if plain is not None else {}
     _line(value, ms_per_step, args, "f64" if precision == "fp64" else "f32_pair/f64_accum",
-          config, roof, baseline)
+          config, roof, baseline, extra=extra)
     return 0
 
 
@@ -371,39 +507,39 @@ def bench_harmonic(args, w) -> int:
     return 0
 
 
-def _member_flops(X, w) -> float:
-    """Algorithmic flops per slice-atom of one LJ path (pairs counted on 2 slices)."""
-    ppa = pairs_per_atom(X, w.box, w.cutoff, n_sample=2)
+def _member_flops(Xs, w) -> float:
+    """Algorithmic flops per slice-atom of one LJ path (pairs counted on the given slices)."""
+    ppa = pairs_per_atom(Xs, w.box, w.cutoff, n_sample=Xs.shape[0])
     return ppa * (FLOP_FORCE_PAIR + FLOP_HV_PAIR) + FLOP_SLICE_ATOM
 
 
 def bench_batch(args) -> int:
     """The 64-path batch: one step = one replay of a captured graph holding one
     persistent pamd_batch_action_grad launch over every member."""
-    members = W.batch_members()
-    arrays = [W.tethered_path(m) for m in members]
-    units = sum(m.n_steps * m.n_atoms for m in members)
-    flops = sum(_member_flops(X, m) * m.n_steps * m.n_atoms for X, m in zip(arrays, members))
-    baseline = None
-    if not args.no_cpu_baseline:
-        # the oracle on the largest member (same per-slice work as the GPU's)
-        big = max(range(len(members)), key=lambda p: members[p].n_atoms * members[p].n_steps)
-        baseline = cpu_baseline(arrays[big], members[big])
-        baseline["sample"] = f"member {big} ({members[big].n_atoms} atoms): " + baseline["sample"]
     import torch
     import paper_1907_09529_amd as P
     P.load()
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    members = W.batch_members()
+    units = sum(m.n_steps * m.n_atoms for m in members)
+    t0 = time.perf_counter()
+    arrays = [input_path(args, m, P, torch, dev)[0] for m in members]
+    print(f"[bench] {len(members)} member inputs on the GPU: {time.perf_counter() - t0:.1f} s",
+          file=sys.stderr, flush=True)
+    flops = sum(_member_flops(X[[0, X.shape[0] - 1]].cpu().numpy(), m) * m.n_steps * m.n_atoms
+                for X, m in zip(arrays, members))
+    big = max(range(len(members)), key=lambda p: members[p].n_atoms * members[p].n_steps)
+    host_big = arrays[big][:min(members[big].n_steps + 1, 4097)].cpu().numpy()
     paths, pots = [], []
     for m in members:
         paths.append(P.make_path(m.n_steps, m.n_atoms, 3, m.dt, m.D, m.gamma, "fp64"))
         pots.append(P.make_potential("lj", eps=m.eps, sigma=m.sigma, rc=m.cutoff, box=m.box))
     b = P.PamdBatch(paths, pots)
-    buf = np.zeros(b.x_offsets[-1])
+    x = torch.zeros(b.x_offsets[-1], dtype=torch.float64, device=dev)
     for p, X in enumerate(arrays):
-        buf[b.x_offsets[p]:b.x_offsets[p] + X.size] = X.ravel()
-    x = torch.from_numpy(buf).to(dev)
+        x[b.x_offsets[p]:b.x_offsets[p] + X.numel()] = X.reshape(-1)
+    del arrays
     grad = torch.zeros_like(x)
     act = torch.empty(len(members), dtype=torch.float64, device=dev)
     b.prepare()
@@ -437,8 +573,14 @@ def bench_batch(args) -> int:
             "flop_per_launch": flops}
     config = {"workload": f"batch of {len(members)} LJ paths, atoms in {{108..2048}}, "
                           f"steps {min(m.n_steps for m in members)}..{max(m.n_steps for m in members)}, "
-                          "one persistent launch, graph-captured",
-              "n_paths": len(members), "slice_atoms": units, "parallelism": "single GPU"}
+                          f"one persistent launch, graph-captured; input: {args.input}",
+              "n_paths": len(members), "slice_atoms": units, "input": args.input,
+              "parallelism": "single GPU"}
+    baseline = None
+    if not args.no_cpu_baseline:
+        # the oracle on the largest member (same per-slice work as the GPU's)
+        baseline = cpu_baseline_child(host_big, workload="batch64", member=big)
+        baseline["sample"] = f"member {big} ({members[big].n_atoms} atoms): " + baseline["sample"]
     _line(units / (ms * 1e-3), ms, args, "f64", config, roof, baseline)
     return 0
 
@@ -449,22 +591,18 @@ def bench_sweep(args) -> int:
     the trial path, accept/commit) followed by action + gradient of the
     committed path, replayed from a captured graph."""
     w = W.workload("sweep4000")
-    print(f"[bench] generating {w.name}: {w.n_steps} steps x {w.n_atoms} atoms", file=sys.stderr,
-          flush=True)
-    X = W.tethered_path(w)
-    baseline = None
-    if not args.no_cpu_baseline:
-        baseline = cpu_baseline(X, w, target_s=12.0, method="cells")
-    flop_unit = _member_flops(X, w)
     import torch
     import paper_1907_09529_amd as P
     P.load()
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    print(f"[bench] input {w.name}: {w.n_steps} steps x {w.n_atoms} atoms ({args.input})",
+          file=sys.stderr, flush=True)
+    x, input_name = input_path(args, w, P, torch, dev)
+    flop_unit = _member_flops(x[[0, w.n_steps // 2, w.n_steps]].cpu().numpy(), w)
+    host_sample = x[:1025].cpu().numpy()
     path = P.make_path(w.n_steps, w.n_atoms, 3, w.dt, w.D, w.gamma, "fp64")
     pot = P.make_potential("lj", eps=w.eps, sigma=w.sigma, rc=w.cutoff, box=w.box)
-    x = torch.from_numpy(X).to(dev)
-    del X
     trial = torch.empty_like(x)
     grad = torch.empty_like(x)
     ex = torch.empty(w.n_steps, dtype=torch.float64, device=dev)
@@ -522,9 +660,13 @@ def bench_sweep(args) -> int:
             "kernel_ms": k_ms, "flop_per_slice_atom": flop_unit, "sweep_ms": g_ms}
     config = {"workload": f"path-sampling sweep, LJ {w.n_atoms} atoms x {w.n_steps} steps, "
                           f"levels {w.l_min}..{w.l_max}, MH move + action + gradient per sweep, "
-                          "graph-captured",
+                          f"graph-captured; input: {input_name}",
               "n_atoms": w.n_atoms, "n_steps": w.n_steps, "sweeps_run": sweeps,
-              "parallelism": "single GPU"}
+              "input": args.input, "parallelism": "single GPU"}
+    baseline = None
+    if not args.no_cpu_baseline:
+        baseline = cpu_baseline_child(host_sample, target_s=12.0, method="cells",
+                                      workload="sweep4000")
     _line(units / (ms * 1e-3), ms, args, "f64", config, roof, baseline)
     return 0
 
@@ -801,17 +943,16 @@ def bench_langevin(args, w, tau: float = 1e-7) -> int:
     4096 steps): one step = one pamd_langevin_step (proposal, action and
     gradient of the proposal, fixed-order Metropolis-Hastings test, commit),
     replayed from a captured graph."""
-    print(f"[bench] generating {w.name}: {w.n_steps} steps x {w.n_atoms} atoms", file=sys.stderr,
-          flush=True)
-    X = W.tethered_path(w)
     import torch
     import paper_1907_09529_amd as P
     P.load()
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    print(f"[bench] input {w.name}: {w.n_steps} steps x {w.n_atoms} atoms ({args.input})",
+          file=sys.stderr, flush=True)
+    x, input_name = input_path(args, w, P, torch, dev)
     path = P.make_path(w.n_steps, w.n_atoms, 3, w.dt, w.D, w.gamma, "fp64")
     pot = P.make_potential("lj", eps=w.eps, sigma=w.sigma, rc=w.cutoff, box=w.box)
-    x = torch.from_numpy(X).to(dev)
     g, y, gy = torch.empty_like(x), torch.empty_like(x), torch.empty_like(x)
     S = torch.empty(1, dtype=torch.float64, device=dev)
     P.pamd_action_grad(path, pot, x, g, action=S)
@@ -863,7 +1004,7 @@ def bench_langevin(args, w, tau: float = 1e-7) -> int:
             "kernel": "lj_fused_kernel (action + gradient of the proposal)", "kernel_ms": k_ms,
             "flop_per_slice_atom": flop_unit, "pairs_per_atom": ppa}
     config = {"workload": f"gradient-informed path move, LJ {w.n_atoms} atoms x {w.n_steps} steps, "
-                          f"tau {tau:g}, graph-replayed moves (tethered-lattice start path)",
+                          f"tau {tau:g}, graph-replayed moves; start path: {input_name}",
               "n_atoms": w.n_atoms, "n_steps": w.n_steps, "tau": tau,
               "acceptance": n_acc / args.steps, "parallelism": "single GPU"}
     _line(units / (ms * 1e-3), ms, args, "f64", config, roof, None,
