@@ -190,6 +190,27 @@ int pamd_action_grad(const pamd_path* path, const pamd_potential* pot, const pam
                      double* action, double* per_step, double* grad,
                      void* ws, size_t ws_bytes, void* stream);
 
+/* Action and gradient for callers that cannot allocate: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  Same
+ * arguments, results and errors as pamd_action_grad except that there is no
+ * workspace: the scratch lives in a static device array of
+ * PAMD_NOALLOC_SCRATCH_BYTES bytes that the library holds on every device it
+ * runs on until the process ends (nothing is allocated or freed per call).
+ * The caller still passes x, grad and the optional outputs.  When the usual
+ * plan's workspace is larger, the call runs the same kernels on fewer
+ * concurrent workgroups (same results, more time); a problem whose scratch
+ * cannot fit even so (e.g. very many steps of a large system) fails with
+ * PAMD_EWORKSPACE before any device work.  Every call on one device shares
+ * that device's array: calls that overlap in time on one device (two streams,
+ * two threads) race and must not be issued; calls in stream order are fine.
+ * No scratch contents need to start at zero, and none survive a call in any
+ * meaningful way. */
+#define PAMD_NOALLOC_SCRATCH_BYTES (128ull << 20)
+int pamd_action_grad_noalloc(const pamd_path* path, const pamd_potential* pot,
+                             const pamd_tuning* tuning, const double* x,
+                             const double* step_weights, double* action, double* per_step,
+                             double* grad, void* stream);
+
 /* Per-step excess action e_n = s_n - s0_n, where s0_n = |Delta_n|^2/(4 D dt)
  * is the force-free (free-particle) term: the quantity the fragment-wise
  * Metropolis-Hastings test needs (Sec. III).  e_n is evaluated as

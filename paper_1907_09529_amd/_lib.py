@@ -28,6 +28,7 @@ PAMD_ALGO_PLAIN = 2
 PAMD_LIST_AUTO = 0
 PAMD_LIST_FULL = 1
 PAMD_LIST_HALF = 2
+PAMD_NOALLOC_SCRATCH_BYTES = 128 << 20
 
 ERROR_NAMES = {PAMD_EINVAL: "PAMD_EINVAL", PAMD_EUNSUPPORTED: "PAMD_EUNSUPPORTED",
                PAMD_EWORKSPACE: "PAMD_EWORKSPACE", PAMD_EHIP: "PAMD_EHIP"}
@@ -75,6 +76,8 @@ _SIGNATURES = {
                               c_size_t, c_void_p]),
     "pamd_action_grad": (c_int32, [_PATH, _POT, _TUNE, c_void_p, c_void_p, c_void_p, c_void_p,
                                    c_void_p, c_void_p, c_size_t, c_void_p]),
+    "pamd_action_grad_noalloc": (c_int32, [_PATH, _POT, _TUNE, c_void_p, c_void_p, c_void_p,
+                                           c_void_p, c_void_p, c_void_p]),
     "pamd_excess_action": (c_int32, [_PATH, _POT, _TUNE, c_void_p, c_void_p, c_void_p,
                                      c_void_p, c_size_t, c_void_p]),
     "pamd_log_norm": (c_double, [_PATH]),

@@ -21,6 +21,7 @@ from ._lib import (PamdPath, PamdPotential, PamdTuning, PamdLaunch, PamdError, P
 __all__ = [
     "PamdPath", "PamdPotential", "PamdTuning", "PamdLaunch", "PamdError", "make_path",
     "make_potential", "make_tuning", "pamd_workspace_size", "pamd_launch_info", "pamd_action", "pamd_action_grad",
+    "pamd_action_grad_noalloc",
     "pamd_excess_action", "pamd_log_norm", "pamd_mh_workspace_size", "pamd_mh_step",
     "pamd_em_workspace_size", "pamd_em_integrate", "pamd_shift", "pamd_run_workspace_size",
     "pamd_run", "pamd_langevin_workspace_size", "pamd_langevin_step", "pamd_autotune", "PamdBatch", "PamdGraph", "workspace",
@@ -175,6 +176,17 @@ def pamd_action_grad(path, pot, x, grad, action=None, per_step=None, step_weight
     ws, _ = _ws(path, pot, tuning, ws)
     _call("pamd_action_grad", ctypes.byref(path), ctypes.byref(pot), _ref(tuning), *args,
               _ptr(ws, None, "ws"), ctypes.c_size_t(ws.numel()), _stream(stream))
+
+
+def pamd_action_grad_noalloc(path, pot, x, grad, action=None, per_step=None,
+                             step_weights=None, tuning=None, stream=None):
+    """pamd_action_grad without a workspace (the library's static scratch)."""
+    _call("pamd_action_grad_noalloc", ctypes.byref(path), ctypes.byref(pot), _ref(tuning),
+          _ptr(x, name="x", numel=_path_elems(path)),
+          _ptr(step_weights, name="step_weights", numel=path.n_steps),
+          _ptr(action, name="action", numel=1),
+          _ptr(per_step, name="per_step", numel=path.n_steps),
+          _ptr(grad, name="grad", numel=_path_elems(path)), _stream(stream))
 
 
 def pamd_excess_action(path, pot, x, excess, per_step=None, ws=None, tuning=None, stream=None):

@@ -188,7 +188,7 @@ size_t bump(size_t& cur, size_t bytes) {
 }
 
 int make_plan(const pamd_path* p, const pamd_potential* v, const pamd_tuning* t_in, bool mh,
-              Plan& P) {
+              Plan& P, int grid_cap = kMaxGrid) {
   int rc;
   if ((rc = check_path(p)) || (rc = check_pot(p, v)) || (rc = check_tuning(t_in))) return rc;
   pamd_tuning t{};
@@ -252,7 +252,7 @@ int make_plan(const pamd_path* p, const pamd_potential* v, const pamd_tuning* t_
     }
     P.tile = (int)std::min<int64_t>(tile, P.steps);
     P.n_tiles = (int)((P.steps + P.tile - 1) / P.tile);
-    P.grid = std::min(P.n_tiles, kMaxGrid);
+    P.grid = std::min(P.n_tiles, std::max(1, std::min(grid_cap, kMaxGrid)));
     P.off_bnd = bump(cur, sizeof(double) * 3 * N * (size_t)std::max(0, P.n_tiles - 1));
     // neighbour list, then the exact list; both with one spare chunk per atom
     // neighbour lists ((kmax + 8) per atom) and exact lists (up to two rows
@@ -568,6 +568,82 @@ int pamd_excess_action(const pamd_path* p, const pamd_potential* v, const pamd_t
   if (!excess) return fail(PAMD_EINVAL, "excess is NULL");
   if ((rc = check_ws(P, ws, ws_bytes))) return rc;
   return evaluate(p, v, P, x, nullptr, nullptr, per_step, nullptr, excess, MODE_EXCESS, ws,
+                  (hipStream_t)stream);
+}
+
+// ---------------------------------------------------------------------------
+// Action and gradient without a caller workspace (see pamd.h)
+// ---------------------------------------------------------------------------
+}  // extern "C"
+
+namespace {
+// Scratch of pamd_action_grad_noalloc: one array per device, loaded with the
+// code object and held until the process ends.  Host code never uses the
+// array's name as an address: hipGetSymbolAddress gives each device's copy.
+static __device__ __align__(256) unsigned char scratch[PAMD_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current device's scratch (looked up once per device).
+int scratch_address(void** out) {
+  int dev = 0;
+  PAMD_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(PAMD_EUNSUPPORTED, "device index %d out of range", dev);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    PAMD_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) return fail(PAMD_EHIP, "hipGetSymbolAddress returned NULL for the scratch array");
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return PAMD_OK;
+}
+
+// The largest plan whose workspace fits the static scratch: the persistent
+// grid shrinks (tiles are taken in a grid-stride loop, so results are the
+// same) until it fits; PAMD_EWORKSPACE when even one workgroup's does not.
+int noalloc_plan(const pamd_path* p, const pamd_potential* v, const pamd_tuning* t, Plan& P) {
+  int rc = make_plan(p, v, t, false, P);
+  if (rc) return rc;
+  if (P.total <= PAMD_NOALLOC_SCRATCH_BYTES) return PAMD_OK;
+  if (P.kind == PAMD_LJ && P.algo == PAMD_ALGO_FUSED && P.grid > 1) {
+    int lo = 1, hi = P.grid - 1, best = 0;
+    while (lo <= hi) {
+      const int mid = (lo + hi) / 2;
+      Plan Q;
+      if ((rc = make_plan(p, v, t, false, Q, mid))) return rc;
+      if (Q.total <= PAMD_NOALLOC_SCRATCH_BYTES) {
+        best = mid;
+        lo = mid + 1;
+      } else {
+        hi = mid - 1;
+      }
+    }
+    if (best > 0) return make_plan(p, v, t, false, P, best);
+  }
+  return fail(PAMD_EWORKSPACE,
+              "problem needs %zu bytes of scratch, more than the %llu-byte static array of "
+              "pamd_action_grad_noalloc; use pamd_action_grad with a workspace",
+              P.total, (unsigned long long)PAMD_NOALLOC_SCRATCH_BYTES);
+}
+}  // namespace
+
+extern "C" {
+
+int pamd_action_grad_noalloc(const pamd_path* p, const pamd_potential* v, const pamd_tuning* t,
+                             const double* x, const double* w, double* action, double* per_step,
+                             double* grad, void* stream) {
+  Plan P;
+  int rc = noalloc_plan(p, v, t, P);
+  if (rc) return rc;
+  if (!x) return fail(PAMD_EINVAL, "x is NULL");
+  if (!grad) return fail(PAMD_EINVAL, "grad is NULL");
+  void* ws = nullptr;
+  if ((rc = scratch_address(&ws))) return rc;
+  return evaluate(p, v, P, x, w, action, per_step, grad, nullptr, MODE_GRAD, ws,
                   (hipStream_t)stream);
 }
 

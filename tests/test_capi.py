@@ -352,3 +352,18 @@ def test_launch_info_reports_the_plan():
     bad = lj_path(n_steps=0)
     assert lib.pamd_launch_info(ctypes.byref(bad), ctypes.byref(pot), None,
                                 ctypes.byref(_lib.PamdLaunch())) == _lib.PAMD_EINVAL
+
+
+@cpu_only
+def test_noalloc_refuses_problems_beyond_its_static_scratch():
+    lib = P.load()
+    path = lj_path(n_steps=1 << 22, n_atoms=4000)
+    pot = lj_pot(box=(4000 / 0.8442) ** (1 / 3))
+    code = lib.pamd_action_grad_noalloc(ctypes.byref(path), ctypes.byref(pot), None, FAKE, None,
+                                        None, None, FAKE, None)
+    assert code == _lib.PAMD_EWORKSPACE
+    assert b"static" in lib.pamd_last_error()
+    # invalid arguments are refused as by pamd_action_grad
+    small = lj_path(n_steps=4)
+    assert lib.pamd_action_grad_noalloc(ctypes.byref(small), ctypes.byref(pot), None, None, None,
+                                        None, None, FAKE, None) == _lib.PAMD_EINVAL
