@@ -244,6 +244,7 @@ def _parser():
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--skin", type=float, default=0.0)
     ap.add_argument("--block", type=int, default=0)
+    ap.add_argument("--slots", type=int, default=0, help="LDS slot arrays (0 = library choice)")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="after timing, run one device copy of this many MiB (for counter calibration)")
     ap.add_argument("--input", choices=["em", "tethered"], default="em",
@@ -345,9 +346,9 @@ def bench_path(args, w) -> int:
     pot = P.make_potential("lj", eps=w.eps, sigma=w.sigma, rc=w.cutoff, box=w.box)
     if args.variant == "plain":
         tuning = P.make_tuning("plain")
-    elif args.list != "auto" or args.tile or args.skin or args.block:
+    elif args.list != "auto" or args.tile or args.skin or args.block or args.slots:
         tuning = P.make_tuning("fused", block=args.block, tile=args.tile, skin=args.skin,
-                               neighbour_list=args.list)
+                               neighbour_list=args.list, slot_arrays=args.slots)
     else:
         tuning = None
     grad = torch.empty_like(x)

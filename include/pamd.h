@@ -132,7 +132,11 @@ typedef struct pamd_path {
  *                  more than skin/2 from where the list was built
  *   max_neighbours capacity of each atom's list; an atom whose list would
  *                  overflow falls back to a scan over all atoms (still exact)
- *   neighbour_list PAMD_LIST_* (fused); half lists need n_atoms <= 2 * block */
+ *   neighbour_list PAMD_LIST_* (fused); half lists need n_atoms <= 2 * block
+ *   slot_arrays    LDS copies of the slice (fused): 2 = the next slice loads
+ *                  into a second array while the current one is in use, 1 =
+ *                  one array (less shared memory, so more workgroups fit on a
+ *                  compute unit), 0 = the library's choice */
 typedef struct pamd_tuning {
   int32_t algo;
   int32_t block;
@@ -140,7 +144,7 @@ typedef struct pamd_tuning {
   int32_t max_neighbours;
   double skin;
   int32_t neighbour_list;
-  int32_t reserved0;
+  int32_t slot_arrays;
 } pamd_tuning;
 
 /* Bytes of workspace needed by pamd_action / pamd_action_grad /

@@ -48,7 +48,7 @@ class PamdPath(ctypes.Structure):
 class PamdTuning(ctypes.Structure):
     _fields_ = [("algo", c_int32), ("block", c_int32), ("tile", c_int32),
                 ("max_neighbours", c_int32), ("skin", c_double), ("neighbour_list", c_int32),
-                ("reserved0", c_int32)]
+                ("slot_arrays", c_int32)]
 
 
 class PamdLaunch(ctypes.Structure):

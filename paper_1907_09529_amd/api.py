@@ -48,10 +48,11 @@ def make_potential(kind: str, k: float = 1.0, eps: float = 1.0, sigma: float = 1
 
 
 def make_tuning(algo: str = "auto", block: int = 0, tile: int = 0, max_neighbours: int = 0,
-                skin: float = 0.0, neighbour_list: str = "auto") -> PamdTuning:
+                skin: float = 0.0, neighbour_list: str = "auto", slot_arrays: int = 0) -> PamdTuning:
     a = {"auto": PAMD_ALGO_AUTO, "fused": PAMD_ALGO_FUSED, "plain": PAMD_ALGO_PLAIN}[algo]
     nl = {"auto": 0, "full": 1, "half": 2}[neighbour_list]
-    return PamdTuning(a, int(block), int(tile), int(max_neighbours), float(skin), nl, 0)
+    return PamdTuning(a, int(block), int(tile), int(max_neighbours), float(skin), nl,
+                      int(slot_arrays))
 
 
 def _ref(s):

@@ -107,6 +107,8 @@ int check_tuning(const pamd_tuning* t) {
   if (!std::isfinite(t->skin)) return fail(PAMD_EINVAL, "skin must be finite");
   if (t->neighbour_list < PAMD_LIST_AUTO || t->neighbour_list > PAMD_LIST_HALF)
     return fail(PAMD_EINVAL, "unknown neighbour_list %d", t->neighbour_list);
+  if (t->slot_arrays < 0 || t->slot_arrays > 2)
+    return fail(PAMD_EINVAL, "slot_arrays must be 0, 1 or 2 (got %d)", t->slot_arrays);
   return PAMD_OK;
 }
 
@@ -224,9 +226,11 @@ int make_plan(const pamd_path* p, const pamd_potential* v, const pamd_tuning* t_
     P.half = list == PAMD_LIST_HALF;  // automatic choice: full lists (repeatable, as fast)
     if (P.half && N > fused_half_slots() * P.block)
       return fail(PAMD_EUNSUPPORTED, "half lists need n_atoms <= %d * block", fused_half_slots());
-    // residuals in LDS with two slot arrays when they fit, else with one,
-    // else in global scratch
-    if (fused_cells_fit(L, radius, N, P.block, true, P.half, &P.cells, &P.lds, true)) {
+    // residuals in LDS with two slot arrays when they fit (unless one is
+    // asked for), else with one, else in global scratch
+    const int slots = t.slot_arrays ? t.slot_arrays
+                                    : (have_cache && cached.slot_arrays ? cached.slot_arrays : 0);
+    if (slots != 1 && fused_cells_fit(L, radius, N, P.block, true, P.half, &P.cells, &P.lds, true)) {
       P.r_in_lds = true;
       P.lds2 = true;
     } else if (fused_cells_fit(L, radius, N, P.block, true, P.half, &P.cells, &P.lds, false)) {
@@ -1017,16 +1021,20 @@ int pamd_autotune(const pamd_path* p, const pamd_potential* v, const double* x,
         if (b >= 64 && b <= 1024 && std::find(blocks.begin(), blocks.end(), b) == blocks.end())
           blocks.push_back(b);
       for (int b : blocks)
-        for (int tile : {4, 8, 16, 32})
-          for (double skin : {0.2, 0.3, 0.45}) {
-            pamd_tuning c{};
-            c.algo = PAMD_ALGO_FUSED;
-            c.block = b;
-            c.tile = tile;
-            c.skin = skin * v->sigma;
-            c.neighbour_list = list;
-            cands.push_back(c);
-          }
+        for (int slots : {2, 1}) {
+          if (slots == 1 && b > 512) continue;  // one array only pays when workgroups share a CU
+          for (int tile : {4, 8, 16, 32})
+            for (double skin : {0.2, 0.3, 0.45}) {
+              pamd_tuning c{};
+              c.algo = PAMD_ALGO_FUSED;
+              c.block = b;
+              c.tile = tile;
+              c.skin = skin * v->sigma;
+              c.neighbour_list = list;
+              c.slot_arrays = slots;
+              cands.push_back(c);
+            }
+        }
     }
   } else {
     cands.push_back(pamd_tuning{});
