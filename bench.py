@@ -516,7 +516,7 @@ def _member_flops(Xs, w) -> float:
 
 def bench_batch(args) -> int:
     """The 64-path batch: one step = one replay of a captured graph holding one
-    persistent pamd_batch_action_grad launch over every member."""
+    persistent pamd_batch_run launch over every member."""
     import torch
     import paper_1907_09529_amd as P
     P.load()
@@ -536,42 +536,69 @@ def bench_batch(args) -> int:
     for m in members:
         paths.append(P.make_path(m.n_steps, m.n_atoms, 3, m.dt, m.D, m.gamma, "fp64"))
         pots.append(P.make_potential("lj", eps=m.eps, sigma=m.sigma, rc=m.cutoff, box=m.box))
-    b = P.PamdBatch(paths, pots)
-    x = torch.zeros(b.x_offsets[-1], dtype=torch.float64, device=dev)
+    b0 = P.PamdBatch(paths, pots)
+    x = torch.zeros(b0.x_offsets[-1], dtype=torch.float64, device=dev)
     for p, X in enumerate(arrays):
-        x[b.x_offsets[p]:b.x_offsets[p] + X.numel()] = X.reshape(-1)
+        x[b0.x_offsets[p]:b0.x_offsets[p] + X.numel()] = X.reshape(-1)
     del arrays
     grad = torch.zeros_like(x)
     act = torch.empty(len(members), dtype=torch.float64, device=dev)
-    b.prepare()
-    s = torch.cuda.Stream()
-    g = P.PamdGraph()
-    torch.cuda.synchronize()
-    with torch.cuda.stream(s):
-        g.begin(s)
-        b.pamd_batch_action_grad(x, act, grad_all=grad, stream=s)
-        g.end(s)
-        for _ in range(args.warmup):
+
+    def time_batch(b):
+        """One persistent launch per replay of a captured graph: (ms per step, graph ms)."""
+        b.prepare()
+        s = torch.cuda.Stream()
+        g = P.PamdGraph()
+        torch.cuda.synchronize()
+        with torch.cuda.stream(s):
+            g.begin(s)
+            b.pamd_batch_run(x, act, grad_all=grad, stream=s)
+            g.end(s)
+            for _ in range(args.warmup):
+                g.launch(s)
+        s.synchronize()
+        ev = HipEvents()
+        hip = HipEvents.hip
+        t0 = time.perf_counter()
+        hip.hipEventRecord(ev.a, ctypes.c_void_p(s.cuda_stream))
+        for _ in range(args.steps):
             g.launch(s)
-    s.synchronize()
-    ev = [HipEvents() for _ in range(2)]
-    hip = HipEvents.hip
+        hip.hipEventRecord(ev.b, ctypes.c_void_p(s.cuda_stream))
+        s.synchronize()
+        t1 = time.perf_counter()
+        out = ((t1 - t0) * 1e3 / args.steps, ev.elapsed_ms() / args.steps)
+        ev.close()
+        g.close()
+        return out
+
+    # the built-in tile heuristic, then tiles from the autotuner: one
+    # pamd_autotune per (atoms, floor(log2 steps)) class of members, on the
+    # class's first member, fills the cache that pamd_batch_create consults
+    ms_h, g_ms_h = time_batch(b0)
+    b0.close()
+    print(f"[bench] heuristic tiles: {g_ms_h:.3f} ms per launch", file=sys.stderr, flush=True)
+    classes = {}
+    for p, m in enumerate(members):
+        classes.setdefault((m.n_atoms, int(math.log2(m.n_steps))), p)
     t0 = time.perf_counter()
-    hip.hipEventRecord(ev[0].a, ctypes.c_void_p(s.cuda_stream))
-    for _ in range(args.steps):
-        g.launch(s)
-    hip.hipEventRecord(ev[0].b, ctypes.c_void_p(s.cuda_stream))
-    s.synchronize()
-    t1 = time.perf_counter()
-    ms = (t1 - t0) * 1e3 / args.steps
-    g_ms = ev[0].elapsed_ms() / args.steps
-    for e in ev:
-        e.close()
-    g.close()
+    for k, p in sorted(classes.items()):
+        view = b0.view(x, p)
+        gview = b0.view(grad, p)
+        wsz = max(P.pamd_workspace_size(paths[p], pots[p],
+                                        P.make_tuning("fused", tile=2, block=bl, skin=0.45,
+                                                      slot_arrays=sl))
+                  for bl in (64, 256, 512, 1024) for sl in (1, 2))
+        best = P.pamd_autotune(paths[p], pots[p], view, gview, P.workspace(wsz))
+        print(f"[bench] autotune class {k}: block {best.block} tile {best.tile} skin {best.skin:.2f} "
+              f"slots {best.slot_arrays} ({time.perf_counter() - t0:.0f} s)", file=sys.stderr, flush=True)
+    b = P.PamdBatch(paths, pots)
+    ms, g_ms = time_batch(b)
+    b.close()
     roof = {"bound": "alu", "achieved": flops / (g_ms * 1e-3) / 1e12, "peak": PEAK_FP64_VALU / 1e12,
             "unit": "TFLOP/s", "frac": flops / (g_ms * 1e-3) / PEAK_FP64_VALU, "traffic": None,
             "kernel": "graph replay (lj_batch_kernel + batch_finalize_kernel)", "kernel_ms": g_ms,
-            "flop_per_launch": flops}
+            "flop_per_launch": flops, "heuristic_tiles_ms": g_ms_h,
+            "autotune_gain": g_ms_h / g_ms, "autotuned_classes": len(classes)}
     config = {"workload": f"batch of {len(members)} LJ paths, atoms in {{108..2048}}, "
                           f"steps {min(m.n_steps for m in members)}..{max(m.n_steps for m in members)}, "
                           f"one persistent launch, graph-captured; input: {args.input}",

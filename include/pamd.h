@@ -72,9 +72,13 @@ extern "C" {
 
 /* ---- force precision (pamd_path.precision) ---- */
 #define PAMD_FP64 0               /* all arithmetic in float64 */
-#define PAMD_FP32_FORCE 1         /* LJ pair functions and pair products in float32; displacements,
-                                     cutoff test, force and Hessian-vector sums, residuals, actions
-                                     and gradients in float64.  Harmonic paths ignore this. */
+#define PAMD_FP32_FORCE 1         /* LJ pair products in float32: each pair's force fs d and
+                                     Hessian-vector term a w + b (d.w) d is rounded to float32
+                                     before it is summed; displacements, cutoff test, the pair
+                                     functions of Eq. 16 (whose r^-12 powers would amplify float32
+                                     rounding twelvefold), the sums, residuals, actions and
+                                     gradients stay float64.  Gradient within 1e-8 of the float64
+                                     result.  Harmonic paths ignore this. */
 
 /* ---- algorithm choice (pamd_tuning.algo) ---- */
 #define PAMD_ALGO_AUTO 0          /* fused */
@@ -238,13 +242,42 @@ const char* pamd_version(void);
 
 /* ------------------------------------------------------------------------
  * Batches: many independent paths (different N, n_atoms, dt, potential) in
- * one persistent launch for all Lennard-Jones members plus one launch for all
- * harmonic members.  A batch is a host object describing the members; its
- * buffers are packed: member p's path starts at element x_offsets[p] of one
- * device array (offsets are multiples of 32 elements), and the same offsets
- * index the packed gradient.  Per-step outputs are packed at step_offsets[p].
- * All members must share one precision.
+ * one persistent launch for all Lennard-Jones members plus one launch per
+ * harmonic member (Eq. 4 evaluated for each path, as pamd_action_grad does
+ * for one).  The work list holds every (path, time tile) pair, largest first;
+ * workgroups take items from it until it is empty.  All members must share
+ * one precision.  Each Lennard-Jones member takes its tile and list skin from
+ * the autotune cache when pamd_autotune has stored an entry for its problem
+ * class (see below), else from a built-in rule.
+ *
+ * Two forms:
+ *   - pamd_batch_action_grad: the paths' own device buffers, passed as host
+ *     arrays of device pointers.  Plans, uploads the work list into `ws` and
+ *     synchronises `stream` before it launches, so it cannot be captured
+ *     into a graph.
+ *   - a batch handle (pamd_batch_create / _layout / _prepare / _run): the
+ *     paths packed into one device array; the work list is uploaded once
+ *     (pamd_batch_prepare), after which pamd_batch_run only enqueues kernels
+ *     and can be captured and replayed (pamd_graph_*).
  * ---------------------------------------------------------------------- */
+
+/* Workspace bytes of pamd_batch_action_grad for these paths (host-only). */
+int pamd_batch_workspace_size(int32_t n_paths, const pamd_path* paths /* host, n_paths */,
+                              const pamd_potential* pots /* host, n_paths */, size_t* bytes);
+
+/* Actions and gradients of n_paths independent paths.
+ *   paths, pots  host arrays of n_paths descriptors (validated as by pamd_action_grad)
+ *   x            host array of n_paths device pointers: path p, layout as for one path
+ *   actions      device, n_paths float64 (written: S of each path)
+ *   grads        host array of n_paths device pointers (gradient p, same shape as x[p],
+ *                written), or NULL for actions only; an entry may be NULL to skip
+ *                that path's gradient
+ *   ws           device workspace of pamd_batch_workspace_size bytes
+ * Buffers of different paths must not overlap. */
+int pamd_batch_action_grad(int32_t n_paths, const pamd_path* paths, const pamd_potential* pots,
+                           const double* const* x, double* actions, double* const* grads,
+                           void* ws, size_t ws_bytes, void* stream);
+
 typedef struct pamd_batch pamd_batch;
 
 int pamd_batch_create(int32_t n_paths, const pamd_path* paths /* host, n_paths */,
@@ -252,26 +285,29 @@ int pamd_batch_create(int32_t n_paths, const pamd_path* paths /* host, n_paths *
                       const pamd_tuning* tuning, pamd_batch** out);
 void pamd_batch_destroy(pamd_batch* batch);
 
-/* Packed layout: x_offsets and step_offsets are host arrays of n_paths + 1
- * int64 (the last entry is the total), either may be NULL.  ws_bytes gets the
- * workspace size. */
+/* Packed layout: member p's path starts at element x_offsets[p] of one device
+ * array (offsets are multiples of 32 elements) and the same offsets index the
+ * packed gradient; per-step arrays are packed at step_offsets[p].  x_offsets
+ * and step_offsets are host arrays of n_paths + 1 int64 (the last entry is the
+ * total), either may be NULL.  ws_bytes gets the workspace size. */
 int pamd_batch_layout(const pamd_batch* batch, int64_t* x_offsets, int64_t* step_offsets,
                       size_t* ws_bytes);
 
-/* Uploads the batch's work list into `ws` (one host-to-device copy).  Call once
- * per workspace before pamd_batch_action_grad, outside any graph capture; the
- * workspace then stays valid for any number of calls on this batch. */
+/* Uploads the batch's work list into `ws` (one host-to-device copy, then a
+ * stream synchronisation).  Call once per workspace before pamd_batch_run,
+ * outside any graph capture; the workspace then stays valid for any number of
+ * calls on this batch. */
 int pamd_batch_prepare(const pamd_batch* batch, void* ws, size_t ws_bytes, void* stream);
 
-/* Actions (and gradients) of every member.
+/* Actions (and gradients) of every member of a prepared batch.
  *   x_all        device, packed paths
  *   weights_all  device, packed per-step weights, or NULL (= all ones)
  *   actions      device, n_paths float64 (written)
  *   per_step_all device, packed per-step actions, or NULL
  *   grad_all     device, packed gradients, or NULL for actions only */
-int pamd_batch_action_grad(const pamd_batch* batch, const double* x_all,
-                           const double* weights_all, double* actions, double* per_step_all,
-                           double* grad_all, void* ws, size_t ws_bytes, void* stream);
+int pamd_batch_run(const pamd_batch* batch, const double* x_all, const double* weights_all,
+                   double* actions, double* per_step_all, double* grad_all, void* ws,
+                   size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------------------
  * Path sampling (Sec. III): one Monte Carlo step of the multilevel sliding-

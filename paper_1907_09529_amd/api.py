@@ -24,7 +24,8 @@ __all__ = [
     "pamd_action_grad_noalloc",
     "pamd_excess_action", "pamd_log_norm", "pamd_mh_workspace_size", "pamd_mh_step",
     "pamd_em_workspace_size", "pamd_em_integrate", "pamd_shift", "pamd_run_workspace_size",
-    "pamd_run", "pamd_langevin_workspace_size", "pamd_langevin_step", "pamd_autotune", "PamdBatch", "PamdGraph", "workspace",
+    "pamd_run", "pamd_langevin_workspace_size", "pamd_langevin_step", "pamd_autotune",
+    "pamd_batch_workspace_size", "pamd_batch_action_grad", "PamdBatch", "PamdGraph", "workspace",
 ]
 
 
@@ -359,12 +360,12 @@ class PamdBatch:
         self.ws = ws
         return ws
 
-    def pamd_batch_action_grad(self, x_all, actions, grad_all=None, per_step_all=None,
-                               weights_all=None, stream=None):
+    def pamd_batch_run(self, x_all, actions, grad_all=None, per_step_all=None,
+                       weights_all=None, stream=None):
         if self.ws is None:
             self.prepare(stream=stream)
         nx, ns = self.x_offsets[-1], self.step_offsets[-1]
-        _call("pamd_batch_action_grad", self._h, _ptr(x_all, name="x_all", numel=nx),
+        _call("pamd_batch_run", self._h, _ptr(x_all, name="x_all", numel=nx),
                   _ptr(weights_all, name="weights_all", numel=ns),
                   _ptr(actions, name="actions", numel=self.n_paths),
                   _ptr(per_step_all, name="per_step_all", numel=ns),
@@ -392,6 +393,42 @@ class PamdBatch:
             self.close()
         except Exception:
             pass
+
+
+def pamd_batch_workspace_size(paths: Sequence[PamdPath], pots: Sequence[PamdPotential]) -> int:
+    n = len(paths)
+    nb = ctypes.c_size_t(0)
+    _call("pamd_batch_workspace_size", ctypes.c_int32(n), (PamdPath * n)(*paths),
+          (PamdPotential * n)(*pots), ctypes.byref(nb))
+    return int(nb.value)
+
+
+def pamd_batch_action_grad(paths: Sequence[PamdPath], pots: Sequence[PamdPotential],
+                           xs: Sequence[torch.Tensor], actions: torch.Tensor,
+                           grads: Optional[Sequence[Optional[torch.Tensor]]] = None,
+                           ws: Optional[torch.Tensor] = None, stream=None):
+    """Actions (and gradients) of independent paths given as separate tensors."""
+    n = len(paths)
+    if len(pots) != n or len(xs) != n or (grads is not None and len(grads) != n):
+        raise ValueError("paths, pots, xs (and grads) must have the same length")
+    xa = [_ptr(x, name=f"xs[{p}]", numel=_path_elems(paths[p])) for p, x in enumerate(xs)]
+    ga = None if grads is None else [
+        _ptr(g, name=f"grads[{p}]", numel=_path_elems(paths[p])) for p, g in enumerate(grads)]
+    act = _ptr(actions, name="actions", numel=n)
+    if ws is None:
+        ws = workspace(pamd_batch_workspace_size(paths, pots))
+    # device checks (as in _call) for the pointer arrays
+    def addr(a):
+        if a is None:
+            return None
+        if not a.t.is_cuda or a.t.device.index != torch.cuda.current_device():
+            raise ValueError(f"{a.name} must be a tensor on the current device")
+        return a.t.data_ptr()
+    x_arr = (ctypes.c_void_p * n)(*[addr(a) for a in xa])
+    g_arr = None if ga is None else (ctypes.c_void_p * n)(*[addr(a) for a in ga])
+    _call("pamd_batch_action_grad", ctypes.c_int32(n), (PamdPath * n)(*paths),
+          (PamdPotential * n)(*pots), x_arr, act, g_arr, _ptr(ws, None, "ws"),
+          ctypes.c_size_t(ws.numel()), _stream(stream))
 
 
 class PamdGraph:

@@ -102,7 +102,11 @@ int pamd_batch_create(int32_t n_paths, const pamd_path* paths, const pamd_potent
     const pamd_path& P = paths[p];
     const pamd_potential& V = pots[p];
     const int N = P.n_atoms;
-    const double skin = skin_in > 0 ? skin_in : 0.5 * V.sigma;
+    // an autotuned single-path launch of the same problem class (pamd_autotune)
+    // gives the member its tile and skin; otherwise the built-in heuristic
+    pamd_tuning tuned{};
+    const bool have = tuning_from_cache(&P, &V, &tuned);
+    const double skin = skin_in > 0 ? skin_in : (have && tuned.skin > 0 ? tuned.skin : 0.5 * V.sigma);
     const double radius = V.rc + skin;
     radii.push_back(radius);
     const double rho = N / (V.box * V.box * V.box);
@@ -110,8 +114,11 @@ int pamd_batch_create(int32_t n_paths, const pamd_path* paths, const pamd_potent
     if (tuning && tuning->max_neighbours > 0) kmax = tuning->max_neighbours;
     kmax = std::max(1, std::min(kmax, std::max(1, N - 1)));
     kmax = (int)align_up((size_t)kmax, 8);  // lists are read in chunks of 8
-    int tile = tuning && tuning->tile > 0 ? tuning->tile
-                                          : (int)std::max(4, std::min(64, (int)std::ceil(16384.0 / N)));
+    int tile = tuning && tuning->tile > 0
+                   ? tuning->tile
+                   : (have && tuned.tile > 0
+                          ? tuned.tile
+                          : (int)std::max(4, std::min(64, (int)std::ceil(16384.0 / N))));
     tile = (int)std::min<int64_t>(tile, P.n_steps);
     BatchMember m;
     std::memset(&m, 0, sizeof(m));
@@ -260,14 +267,16 @@ int pamd_batch_prepare(const pamd_batch* b, void* ws, size_t ws_bytes, void* str
   return PAMD_OK;
 }
 
-int pamd_batch_action_grad(const pamd_batch* b, const double* x_all, const double* w_all,
-                           double* actions, double* per_step_all, double* grad_all, void* ws,
-                           size_t ws_bytes, void* stream) {
-  if (!b) return batch_fail(PAMD_EINVAL, "batch is NULL");
-  if (!x_all || !actions) return batch_fail(PAMD_EINVAL, "x_all and actions must be non-NULL");
-  if (ws_bytes < b->total) return batch_fail(PAMD_EWORKSPACE, "workspace has %zu bytes, %zu needed", ws_bytes, b->total);
-  if (!ws || ((uintptr_t)ws) % kAlign) return batch_fail(PAMD_EWORKSPACE, "workspace must be non-NULL and 256-byte aligned");
-  hipStream_t st = (hipStream_t)stream;
+}  // extern "C"
+
+namespace {
+// The batch's launches.  Packed form: member p at x_all + x_off[p] (gradient
+// likewise in grad_all).  Pointer form (xs != null): member p at xs[p], its
+// gradient at gs[p] (gs or gs[p] null: no gradient), per-step terms in the
+// workspace.
+int run_batch(const pamd_batch* b, const double* x_all, const double* w_all, double* actions,
+              double* per_step_all, double* grad_all, const double* const* xs,
+              double* const* gs, void* ws, hipStream_t st) {
   char* base = (char*)ws;
   double* steps = per_step_all ? per_step_all : (double*)(base + b->off_steps);
   hipError_t e = hipSuccess;
@@ -278,7 +287,7 @@ int pamd_batch_action_grad(const pamd_batch* b, const double* x_all, const doubl
     bb.grad = grad_all;
     bb.per_step = steps;
     bb.bnd = (double*)(base + b->off_bnd);
-    bb.mode = grad_all ? MODE_GRAD : 0;
+    bb.mode = 0;
     bb.pad0 = 0;
     BlockScratch s;
     s.nbr = (uint16_t*)(base + b->off_nbr);
@@ -303,9 +312,9 @@ int pamd_batch_action_grad(const pamd_batch* b, const double* x_all, const doubl
   for (int p : b->ho_ids) {
     const pamd_path& P = b->paths[p];
     HOArgs h;
-    h.x = x_all + b->x_off[p];
+    h.x = xs ? xs[p] : x_all + b->x_off[p];
     h.weights = w_all ? w_all + b->step_off[p] : nullptr;
-    h.grad = grad_all ? grad_all + b->x_off[p] : nullptr;
+    h.grad = xs ? (gs ? gs[p] : nullptr) : (grad_all ? grad_all + b->x_off[p] : nullptr);
     h.per_step = steps + b->step_off[p];
     h.excess = nullptr;
     h.n_steps = P.n_steps;
@@ -314,7 +323,7 @@ int pamd_batch_action_grad(const pamd_batch* b, const double* x_all, const doubl
     h.mu_dt = P.dt / P.gamma;
     h.inv4Ddt = 1.0 / (4.0 * P.D * P.dt);
     h.c = 1.0 / (2.0 * P.D * P.dt);
-    h.mode = grad_all ? MODE_GRAD : 0;
+    h.mode = h.grad ? MODE_GRAD : 0;
     int seg = 1;
     while (seg < 64 && seg < h.n_dof) seg <<= 1;
     h.seg = seg;
@@ -322,6 +331,63 @@ int pamd_batch_action_grad(const pamd_batch* b, const double* x_all, const doubl
     if (e != hipSuccess) return batch_fail(PAMD_EHIP, "batch harmonic launch: %s", hipGetErrorString(e));
   }
   return PAMD_OK;
+}
+
+int check_batch_ws(size_t need, void* ws, size_t ws_bytes) {
+  if (ws_bytes < need) return batch_fail(PAMD_EWORKSPACE, "workspace has %zu bytes, %zu needed", ws_bytes, need);
+  if (!ws || ((uintptr_t)ws) % kAlign) return batch_fail(PAMD_EWORKSPACE, "workspace must be non-NULL and 256-byte aligned");
+  return PAMD_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int pamd_batch_run(const pamd_batch* b, const double* x_all, const double* w_all,
+                   double* actions, double* per_step_all, double* grad_all, void* ws,
+                   size_t ws_bytes, void* stream) {
+  if (!b) return batch_fail(PAMD_EINVAL, "batch is NULL");
+  if (!x_all || !actions) return batch_fail(PAMD_EINVAL, "x_all and actions must be non-NULL");
+  int rc = check_batch_ws(b->total, ws, ws_bytes);
+  if (rc) return rc;
+  return run_batch(b, x_all, w_all, actions, per_step_all, grad_all, nullptr, nullptr, ws,
+                   (hipStream_t)stream);
+}
+
+int pamd_batch_workspace_size(int32_t n_paths, const pamd_path* paths, const pamd_potential* pots,
+                              size_t* bytes) {
+  if (!bytes) return batch_fail(PAMD_EINVAL, "bytes is NULL");
+  pamd_batch* b = nullptr;
+  int rc = pamd_batch_create(n_paths, paths, pots, nullptr, &b);
+  if (rc) return rc;
+  *bytes = b->total;
+  pamd_batch_destroy(b);
+  return PAMD_OK;
+}
+
+int pamd_batch_action_grad(int32_t n_paths, const pamd_path* paths, const pamd_potential* pots,
+                           const double* const* x, double* actions, double* const* grads,
+                           void* ws, size_t ws_bytes, void* stream) {
+  if (n_paths >= 1 && !x) return batch_fail(PAMD_EINVAL, "x (array of path pointers) is NULL");
+  if (n_paths >= 1 && !actions) return batch_fail(PAMD_EINVAL, "actions is NULL");
+  for (int32_t p = 0; p < n_paths && x; ++p)
+    if (!x[p]) return batch_fail(PAMD_EINVAL, "x[%d] is NULL", p);
+  pamd_batch* b = nullptr;
+  int rc = pamd_batch_create(n_paths, paths, pots, nullptr, &b);
+  if (rc) return rc;
+  if ((rc = check_batch_ws(b->total, ws, ws_bytes))) {
+    pamd_batch_destroy(b);
+    return rc;
+  }
+  for (size_t mi = 0; mi < b->members.size(); ++mi) {
+    const int p = b->slots[mi];
+    b->members[mi].x_abs = x[p];
+    b->members[mi].grad_abs = grads ? grads[p] : nullptr;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  rc = pamd_batch_prepare(b, ws, ws_bytes, stream);
+  if (!rc) rc = run_batch(b, nullptr, nullptr, actions, nullptr, nullptr, x, grads, ws, st);
+  pamd_batch_destroy(b);
+  return rc;
 }
 
 }  // extern "C"

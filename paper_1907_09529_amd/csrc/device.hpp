@@ -22,7 +22,6 @@ __device__ __forceinline__ double rsqrt_nr(double x) {
   return y;
 }
 
-__device__ __forceinline__ float rsqrt_f32(float x) { return __builtin_amdgcn_rsqf(x); }
 
 // Minimum-image displacement in a cubic box: d - L * rint(d / L), round half to even.
 __device__ __forceinline__ double min_image(double d, double box, double inv_box) {

@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "pamd.h"
+
 namespace pamd {
 
 // Mode bits of a path evaluation.
@@ -120,6 +122,8 @@ struct BatchMember {
   int64_t x_off;      // into x_all / grad_all
   int64_t step_off;   // into weights_all / per_step_all
   int64_t bnd_off;    // into the workspace boundary buffer
+  const double* x_abs;  // the member's own path and gradient buffers (pointer-array
+  double* grad_abs;     // form); null: the packed buffers at x_off
 };
 
 // Packed buffers of one batch call.
@@ -132,6 +136,9 @@ struct BatchBase {
   int32_t mode;
   int32_t pad0;
 };
+
+// The autotune cache entry for this problem, if pamd_autotune has stored one.
+bool tuning_from_cache(const pamd_path* p, const pamd_potential* v, pamd_tuning* out);
 
 // Shared memory of the fused kernel's workgroup (bytes).
 // With rho in LDS (r_in_lds) there are two slot arrays (two) or one.

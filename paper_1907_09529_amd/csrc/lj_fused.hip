@@ -603,26 +603,21 @@ __device__ __forceinline__ void pass1_part(const PathArgs& a, const TileLDS& L,
     }
     // a rejected pair gets iru = 0, which zeroes every term below
     double px = 0.0, py = 0.0, pz = 0.0;
+    double iru = rsqrt_nr(r2);
+    iru = ok ? iru : 0.0;
+    const double ir2 = iru * iru;
+    const double ir6 = ir2 * ir2 * ir2;
+    const double fsl = fma(ir2 * ir6, fma(k.f12, ir6, -k.f6), k.duc * iru);
     if constexpr (F32) {
-      float iru = rsqrt_f32((float)r2);
-      iru = ok ? iru : 0.0f;
-      const float ir2 = iru * iru;
-      const float sr2 = (float)k.sig2 * ir2;
-      const float sr6 = sr2 * sr2 * sr2;
-      const float fsl = fmaf((float)k.a24_L * (ir2 * sr6), fmaf(2.0f, sr6, -1.0f),
-                             (float)k.duc * iru);
-      px = (double)(fsl * (float)dx);
-      py = (double)(fsl * (float)dy);
-      pz = (double)(fsl * (float)dz);
+      // float32 pair product, float64 sum (pair function in float64)
+      const float f = (float)fsl;
+      px = (double)(f * (float)dx);
+      py = (double)(f * (float)dy);
+      pz = (double)(f * (float)dz);
       fx += px;
       fy += py;
       fz += pz;
     } else {
-      double iru = rsqrt_nr(r2);
-      iru = ok ? iru : 0.0;
-      const double ir2 = iru * iru;
-      const double ir6 = ir2 * ir2 * ir2;
-      const double fsl = fma(ir2 * ir6, fma(k.f12, ir6, -k.f6), k.duc * iru);
       fx = fma(fsl, dx, fx);
       fy = fma(fsl, dy, fy);
       fz = fma(fsl, dz, fz);
@@ -719,21 +714,24 @@ __device__ __forceinline__ void pass2_part(const PathArgs& a, const TileLDS& L, 
     if constexpr (decltype(check)::value) ok = ok && r2 <= k.rc2;
     const double wx = rx - qtx, wy = ry - qty, wz = rz - qtz;
     if constexpr (F32) {
-      float iru = rsqrt_f32((float)r2);
-      iru = ok ? iru : 0.0f;
-      const float ir2 = iru * iru;
-      const float sr2 = (float)k.sig2 * ir2;
-      const float sr6 = sr2 * sr2 * sr2;
-      const float p = ir2 * sr6;
-      const float ducir = (float)k.duc_L * iru;
-      const float fs = fmaf((float)k.a24_L2 * p, fmaf(2.0f, sr6, -1.0f), ducir);
-      const float bv = fmaf((float)k.a96_L2 * p, fmaf(sr6, 7.0f, -2.0f), ducir) * ir2;
-      const float dxf = (float)dx, dyf = (float)dy, dzf = (float)dz;
-      const float wxf = (float)wx, wyf = (float)wy, wzf = (float)wz;
-      const float tt = bv * fmaf(dxf, wxf, fmaf(dyf, wyf, dzf * wzf));
-      const double kx = (double)fmaf(-fs, wxf, tt * dxf);
-      const double ky = (double)fmaf(-fs, wyf, tt * dyf);
-      const double kz = (double)fmaf(-fs, wzf, tt * dzf);
+      // pair functions in float64 (as below), the products with w and d in
+      // float32, the sums in float64
+      double iru;
+      if constexpr (decltype(check)::value)
+        iru = ok ? rsqrt_nr(r2) : 0.0;
+      else
+        iru = rsqrt_nr(fmax(r2, 1e-30));
+      const double ir2 = iru * iru;
+      const double ir6 = ir2 * ir2 * ir2;
+      const double ir8 = ir2 * ir6;
+      const double ducir = k.duc_L * iru;
+      const double fs = fma(ir8, fma(k.s12, ir6, -k.s6), ducir);
+      const double bv = fma(ir8, fma(k.b12, ir6, -k.b6), ducir) * ir2;
+      const float a = (float)(-fs);
+      const float tt = (float)(bv * fma(dx, wx, fma(dy, wy, dz * wz)));
+      const double kx = (double)fmaf(a, (float)wx, tt * (float)dx);
+      const double ky = (double)fmaf(a, (float)wy, tt * (float)dy);
+      const double kz = (double)fmaf(a, (float)wz, tt * (float)dz);
       qx += kx;
       qy += ky;
       qz += kz;
@@ -1129,14 +1127,14 @@ __global__ void __launch_bounds__(1024) lj_action_kernel(PathArgs a, BlockScratc
 
 __device__ __forceinline__ PathArgs member_args(const BatchMember& m, const BatchBase& b) {
   PathArgs a = m.a;
-  a.x = b.x + m.x_off;
+  a.x = m.x_abs ? m.x_abs : b.x + m.x_off;
   a.weights = b.weights ? b.weights + m.step_off : nullptr;
-  a.grad = b.grad ? b.grad + m.x_off : nullptr;
+  a.grad = m.x_abs ? m.grad_abs : (b.grad ? b.grad + m.x_off : nullptr);
   a.per_step = b.per_step + m.step_off;
   a.bnd = b.bnd + m.bnd_off;
   a.excess = nullptr;
-  a.mode = b.mode & ~MODE_EXCESS;
-  if (!b.grad) a.mode &= ~MODE_GRAD;
+  a.mode = (b.mode | MODE_GRAD) & ~MODE_EXCESS;
+  if (!a.grad) a.mode &= ~MODE_GRAD;
   return a;
 }
 

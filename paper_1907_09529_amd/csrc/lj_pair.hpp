@@ -52,133 +52,35 @@ struct PairMath<false> {
   }
 };
 
-// Branch-free pair terms for the fused kernel: `ok` selects the pair (inside
-// the cutoff and a real list entry); rejected pairs contribute exactly zero.
-template <bool F32>
-struct PairSel;
-
-template <>
-struct PairSel<false> {
-  static __device__ __forceinline__ void force(const LJConst& lj, bool ok, double r2, double dx,
-                                               double dy, double dz, double& fx, double& fy,
-                                               double& fz, double& px, double& py, double& pz) {
-    const double ir = rsqrt_nr(ok ? r2 : 1.0);
-    const double ir2 = ir * ir;
-    const double sr2 = lj.sig2 * ir2;
-    const double sr6 = sr2 * sr2 * sr2;
-    double fs = fma(lj.a24 * ir2 * sr6, fma(2.0, sr6, -1.0), lj.duc * ir);
-    fs = ok ? fs : 0.0;
-    px = fs * dx;
-    py = fs * dy;
-    pz = fs * dz;
-    fx += px;
-    fy += py;
-    fz += pz;
-  }
-  static __device__ __forceinline__ void hv(const LJConst& lj, bool ok, double r2, double dx,
-                                            double dy, double dz, double wx, double wy,
-                                            double wz, double& qx, double& qy, double& qz,
-                                            double& kx, double& ky, double& kz) {
-    const double ir = rsqrt_nr(ok ? r2 : 1.0);
-    const double ir2 = ir * ir;
-    const double sr2 = lj.sig2 * ir2;
-    const double sr6 = sr2 * sr2 * sr2;
-    const double c6 = lj.a24 * ir2 * sr6;
-    const double a = -fma(c6, fma(2.0, sr6, -1.0), lj.duc * ir);   // U'/r
-    const double upp = c6 * fma(26.0, sr6, -7.0);                   // U''
-    double b = (upp - a) * ir2;
-    const double aa = ok ? a : 0.0;
-    b = ok ? b : 0.0;
-    const double t = b * fma(dx, wx, fma(dy, wy, dz * wz));
-    kx = fma(aa, wx, t * dx);
-    ky = fma(aa, wy, t * dy);
-    kz = fma(aa, wz, t * dz);
-    qx += kx;
-    qy += ky;
-    qz += kz;
-  }
-};
-
-template <>
-struct PairSel<true> {
-  static __device__ __forceinline__ void force(const LJConst& lj, bool ok, double r2, double dx,
-                                               double dy, double dz, double& fx, double& fy,
-                                               double& fz, double& px, double& py, double& pz) {
-    const float ir = rsqrt_f32(ok ? (float)r2 : 1.0f);
-    const float ir2 = ir * ir;
-    const float sr2 = (float)lj.sig2 * ir2;
-    const float sr6 = sr2 * sr2 * sr2;
-    float fs = fmaf((float)lj.a24 * ir2 * sr6, fmaf(2.0f, sr6, -1.0f), (float)lj.duc * ir);
-    fs = ok ? fs : 0.0f;
-    px = (double)(fs * (float)dx);
-    py = (double)(fs * (float)dy);
-    pz = (double)(fs * (float)dz);
-    fx += px;
-    fy += py;
-    fz += pz;
-  }
-  static __device__ __forceinline__ void hv(const LJConst& lj, bool ok, double r2, double dx,
-                                            double dy, double dz, double wx, double wy,
-                                            double wz, double& qx, double& qy, double& qz,
-                                            double& kx, double& ky, double& kz) {
-    const float ir = rsqrt_f32(ok ? (float)r2 : 1.0f);
-    const float ir2 = ir * ir;
-    const float sr2 = (float)lj.sig2 * ir2;
-    const float sr6 = sr2 * sr2 * sr2;
-    const float c6 = (float)lj.a24 * ir2 * sr6;
-    const float a = -fmaf(c6, fmaf(2.0f, sr6, -1.0f), (float)lj.duc * ir);
-    const float upp = c6 * fmaf(26.0f, sr6, -7.0f);
-    float b = (upp - a) * ir2;
-    const float aa = ok ? a : 0.0f;
-    b = ok ? b : 0.0f;
-    const float dxf = (float)dx, dyf = (float)dy, dzf = (float)dz;
-    const float wxf = (float)wx, wyf = (float)wy, wzf = (float)wz;
-    const float t = b * fmaf(dxf, wxf, fmaf(dyf, wyf, dzf * wzf));
-    kx = (double)fmaf(aa, wxf, t * dxf);
-    ky = (double)fmaf(aa, wyf, t * dyf);
-    kz = (double)fmaf(aa, wzf, t * dzf);
-    qx += kx;
-    qy += ky;
-    qz += kz;
-  }
-};
-
 template <>
 struct PairMath<true> {
-  // Pair functions and products in float32; the displacement (and the cutoff
-  // test, done by the caller) stay in float64, sums are accumulated in float64.
-  static __device__ __forceinline__ void forcef(const LJConst& lj, float r2, float& fs,
-                                                float& ir2, float& sr6) {
-    const float ir = rsqrt_f32(r2);
-    ir2 = ir * ir;
-    const float sr2 = (float)lj.sig2 * ir2;
-    sr6 = sr2 * sr2 * sr2;
-    fs = fmaf((float)lj.a24 * ir2 * sr6, fmaf(2.0f, sr6, -1.0f), (float)lj.duc * ir);
-  }
+  // Float32 pair products: the pair functions (r^-2, the r^-6 / r^-12 chain,
+  // U'/r, U'') stay in float64, since their powers amplify float32 rounding
+  // about twelvefold; the products of the pair scalars with the displacement
+  // and with w (fs d, and a w + b (d.w) d) are formed in float32 and summed
+  // in float64.
   static __device__ __forceinline__ void accum_force(const LJConst& lj, double dx, double dy,
                                                      double dz, double r2, double& fx,
                                                      double& fy, double& fz) {
-    float fs, ir2, sr6;
-    forcef(lj, (float)r2, fs, ir2, sr6);
-    fx += (double)(fs * (float)dx);
-    fy += (double)(fs * (float)dy);
-    fz += (double)(fs * (float)dz);
+    double fs, ir2, sr6;
+    PairMath<false>::force(lj, r2, fs, ir2, sr6);
+    const float f = (float)fs;
+    fx += (double)(f * (float)dx);
+    fy += (double)(f * (float)dy);
+    fz += (double)(f * (float)dz);
   }
   static __device__ __forceinline__ void accum_hv(const LJConst& lj, double dx, double dy,
                                                   double dz, double r2, double wx, double wy,
                                                   double wz, double& qx, double& qy,
                                                   double& qz) {
-    float fs, ir2, sr6;
-    forcef(lj, (float)r2, fs, ir2, sr6);
-    const float a = -fs;
-    const float upp = (float)lj.a24 * ir2 * sr6 * fmaf(26.0f, sr6, -7.0f);
-    const float b = (upp - a) * ir2;
-    const float dxf = (float)dx, dyf = (float)dy, dzf = (float)dz;
-    const float wxf = (float)wx, wyf = (float)wy, wzf = (float)wz;
-    const float t = b * fmaf(dxf, wxf, fmaf(dyf, wyf, dzf * wzf));
-    qx += (double)fmaf(a, wxf, t * dxf);
-    qy += (double)fmaf(a, wyf, t * dyf);
-    qz += (double)fmaf(a, wzf, t * dzf);
+    double fs, ir2, sr6;
+    PairMath<false>::force(lj, r2, fs, ir2, sr6);
+    const double upp = lj.a24 * ir2 * sr6 * fma(26.0, sr6, -7.0);
+    const float a = (float)(-fs);
+    const float t = (float)((upp + fs) * ir2 * fma(dx, wx, fma(dy, wy, dz * wz)));
+    qx += (double)fmaf(a, (float)wx, t * (float)dx);
+    qy += (double)fmaf(a, (float)wy, t * (float)dy);
+    qz += (double)fmaf(a, (float)wz, t * (float)dz);
   }
 };
 

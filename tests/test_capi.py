@@ -367,3 +367,28 @@ def test_noalloc_refuses_problems_beyond_its_static_scratch():
     small = lj_path(n_steps=4)
     assert lib.pamd_action_grad_noalloc(ctypes.byref(small), ctypes.byref(pot), None, None, None,
                                         None, None, FAKE, None) == _lib.PAMD_EINVAL
+
+
+@cpu_only
+def test_pointer_array_batch_validation():
+    lib = P.load()
+    paths = (_lib.PamdPath * 2)(lj_path(n_steps=8, n_atoms=108),
+                                lj_path(n_steps=5, n_atoms=108))
+    pots = (_lib.PamdPotential * 2)(lj_pot(box=(108 / 0.8442) ** (1 / 3)),
+                                    lj_pot(box=(108 / 0.8442) ** (1 / 3)))
+    need = ctypes.c_size_t(0)
+    assert lib.pamd_batch_workspace_size(2, paths, pots, ctypes.byref(need)) == _lib.PAMD_OK
+    assert need.value > 0
+    xs = (ctypes.c_void_p * 2)(0x10000000, 0x20000000)
+    gs = (ctypes.c_void_p * 2)(0x30000000, None)
+    def call(x=xs, act=FAKE, g=gs, ws=FAKE, nbytes=need.value, n=2):
+        return lib.pamd_batch_action_grad(n, paths, pots, x, act, g, ws, ctypes.c_size_t(nbytes),
+                                          None)
+    assert call(x=None) == _lib.PAMD_EINVAL
+    assert call(act=None) == _lib.PAMD_EINVAL
+    assert call(x=(ctypes.c_void_p * 2)(0x10000000, None)) == _lib.PAMD_EINVAL
+    assert call(nbytes=need.value - 1) == _lib.PAMD_EWORKSPACE
+    assert call(ws=FAKE_BAD) == _lib.PAMD_EWORKSPACE
+    assert call(n=0) == _lib.PAMD_EINVAL
+    bad = (_lib.PamdPath * 2)(lj_path(n_steps=8, n_atoms=108), lj_path(n_steps=0, n_atoms=108))
+    assert lib.pamd_batch_workspace_size(2, bad, pots, ctypes.byref(need)) == _lib.PAMD_EINVAL

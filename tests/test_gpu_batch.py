@@ -33,7 +33,7 @@ def test_small_mixed_batch_vs_oracle(device):
     grad = torch.zeros_like(x)
     act = torch.empty(len(members), dtype=torch.float64, device="cuda")
     ps = torch.empty(b.step_offsets[-1], dtype=torch.float64, device="cuda")
-    b.pamd_batch_action_grad(x, act, grad_all=grad, per_step_all=ps)
+    b.pamd_batch_run(x, act, grad_all=grad, per_step_all=ps)
     torch.cuda.synchronize()
     for p, (w, X) in enumerate(members):
         s_ref, g_ref = oracle_full(w, X)
@@ -42,9 +42,33 @@ def test_small_mixed_batch_vs_oracle(device):
         assert rel_inf(b.view(grad, p).cpu().numpy(), g_ref) <= 1e-10, p
     # repeated calls reuse the prepared workspace and give identical results
     act2 = torch.empty_like(act)
-    b.pamd_batch_action_grad(x, act2)
+    b.pamd_batch_run(x, act2)
     torch.cuda.synchronize()
     assert torch.equal(act, act2)
+
+
+def test_pointer_array_form_vs_oracle(device):
+    """pamd_batch_action_grad: each path in its own buffer (host arrays of
+    device pointers), one member without a gradient; against the oracle."""
+    members = [em_input("lj108", n_steps=40), em_input("ho1d", n_steps=50),
+               em_input("lj108", n_atoms=256, n_steps=13), em_input("lj27", n_steps=21)]
+    paths, pots = zip(*(lib_descriptors(w) for w, _ in members))
+    xs = [torch.from_numpy(np.ascontiguousarray(X)).cuda() for _, X in members]
+    grads = [torch.full_like(x, float("nan")) for x in xs]
+    grads[2] = None
+    act = torch.empty(len(members), dtype=torch.float64, device="cuda")
+    P.pamd_batch_action_grad(list(paths), list(pots), xs, act, grads)
+    torch.cuda.synchronize()
+    for p, (w, X) in enumerate(members):
+        s_ref, g_ref = oracle_full(w, X)
+        assert rel(float(act[p]), math.fsum(s_ref.tolist())) <= 1e-12, p
+        if grads[p] is not None:
+            assert rel_inf(grads[p].cpu().numpy(), g_ref) <= 1e-10, p
+    # actions only
+    act2 = torch.empty_like(act)
+    P.pamd_batch_action_grad(list(paths), list(pots), xs, act2)
+    torch.cuda.synchronize()
+    assert torch.allclose(act, act2, rtol=1e-13, atol=0.0)
 
 
 def test_batch64_full_workload(device):
@@ -62,7 +86,7 @@ def test_batch64_full_workload(device):
     x = pack(b, arrays)
     grad = torch.zeros_like(x)
     act = torch.empty(len(ws), dtype=torch.float64, device="cuda")
-    b.pamd_batch_action_grad(x, act, grad_all=grad)
+    b.pamd_batch_run(x, act, grad_all=grad)
     torch.cuda.synchronize()
     for p, w in enumerate(ws):
         g1 = torch.empty_like(b.view(x, p))
@@ -91,7 +115,7 @@ def test_batch_graph_replays_match_eager(device):
     x = pack(b, [X for _, X in members])
     ref_g = torch.zeros_like(x)
     ref_a = torch.empty(len(members), dtype=torch.float64, device="cuda")
-    b.pamd_batch_action_grad(x, ref_a, grad_all=ref_g)
+    b.pamd_batch_run(x, ref_a, grad_all=ref_g)
     torch.cuda.synchronize()
     grad = torch.zeros_like(x)
     act = torch.empty_like(ref_a)
@@ -99,7 +123,7 @@ def test_batch_graph_replays_match_eager(device):
     g = P.PamdGraph()
     with torch.cuda.stream(s):
         g.begin(s)
-        b.pamd_batch_action_grad(x, act, grad_all=grad, stream=s)
+        b.pamd_batch_run(x, act, grad_all=grad, stream=s)
         g.end(s)
     for _ in range(3):
         grad.zero_()

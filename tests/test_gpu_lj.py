@@ -3,12 +3,12 @@
 Tolerances (FP64 path): action and every per-step term within 1e-12 relative;
 gradient within 1e-10 in the normwise sense ||g - g_ref||_inf / ||g_ref||_inf.
 
-FP32-force variant: float32 pair functions carry a relative error of a few
-float32 ulps that the 12th power of sigma/r amplifies about twelve-fold
-(~1e-6 per pair term); the gradient sees it through
-c (dt/gamma) dF = dF / 2 and through the float32 Hessian terms.  For these
-workloads that bounds the normwise gradient error near 1e-6, so the test
-holds it to 2e-6 and the action to 1e-8, and prints both measured errors.
+FP32-force variant: the pair functions stay in float64 and only the pair
+products (fs d in the force, a w + b (d.w) d in the Hessian-vector product)
+are rounded to float32 before the float64 sums.  The gradient is held to the
+variant's bound of 1e-8 and the action to 1e-9 (a float32 rounding of each
+pair force moves s_n by ~1e-11 relative on these workloads); both measured
+errors are printed.
 """
 import math
 
@@ -27,7 +27,8 @@ pytestmark = pytest.mark.gpu
 
 ACTION_TOL = 1e-12
 GRAD_TOL = 1e-10
-GRAD_TOL_F32 = 2e-6
+GRAD_TOL_F32 = 1e-8
+ACTION_TOL_F32 = 1e-9
 
 
 def run(w, X, precision="fp64", tuning=None, weights=None):
@@ -54,8 +55,8 @@ def check(w, X, tuning=None, precision="fp64", weights=None, ref=None):
         assert err_s <= ACTION_TOL, err_s
         assert np.max(np.abs(s - s_ref) / np.abs(s_ref)) <= ACTION_TOL
     else:
-        print(f"FP32-force action relative error vs FP64 oracle: {err_s:.3e}")
-        assert err_s <= 1e-8
+        print(f"FP32-force vs FP64 oracle: action {err_s:.3e}, gradient {err_g:.3e}")
+        assert err_s <= ACTION_TOL_F32
     assert err_g <= gtol, err_g
     return err_s, err_g
 
