@@ -571,34 +571,21 @@ def bench_batch(args) -> int:
         g.close()
         return out
 
-    # the built-in tile heuristic, then tiles from the autotuner: one
-    # pamd_autotune per (atoms, floor(log2 steps)) class of members, on the
-    # class's first member, fills the cache that pamd_batch_create consults
+    # the built-in tile rule, then the batch autotuner's choice (it times the
+    # persistent launch itself for each member-tile policy)
     ms_h, g_ms_h = time_batch(b0)
-    b0.close()
-    print(f"[bench] heuristic tiles: {g_ms_h:.3f} ms per launch", file=sys.stderr, flush=True)
-    classes = {}
-    for p, m in enumerate(members):
-        classes.setdefault((m.n_atoms, int(math.log2(m.n_steps))), p)
+    print(f"[bench] built-in tiles: {g_ms_h:.3f} ms per launch", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
-    for k, p in sorted(classes.items()):
-        view = b0.view(x, p)
-        gview = b0.view(grad, p)
-        wsz = max(P.pamd_workspace_size(paths[p], pots[p],
-                                        P.make_tuning("fused", tile=2, block=bl, skin=0.45,
-                                                      slot_arrays=sl))
-                  for bl in (64, 256, 512, 1024) for sl in (1, 2))
-        best = P.pamd_autotune(paths[p], pots[p], view, gview, P.workspace(wsz))
-        print(f"[bench] autotune class {k}: block {best.block} tile {best.tile} skin {best.skin:.2f} "
-              f"slots {best.slot_arrays} ({time.perf_counter() - t0:.0f} s)", file=sys.stderr, flush=True)
-    b = P.PamdBatch(paths, pots)
-    ms, g_ms = time_batch(b)
-    b.close()
+    budget, skin = b0.autotune(x, grad)
+    print(f"[bench] batch autotune: tile budget {budget:g} atom-steps, skin {skin:g} sigma "
+          f"({time.perf_counter() - t0:.1f} s)", file=sys.stderr, flush=True)
+    ms, g_ms = time_batch(b0)
+    b0.close()
     roof = {"bound": "alu", "achieved": flops / (g_ms * 1e-3) / 1e12, "peak": PEAK_FP64_VALU / 1e12,
             "unit": "TFLOP/s", "frac": flops / (g_ms * 1e-3) / PEAK_FP64_VALU, "traffic": None,
             "kernel": "graph replay (lj_batch_kernel + batch_finalize_kernel)", "kernel_ms": g_ms,
-            "flop_per_launch": flops, "heuristic_tiles_ms": g_ms_h,
-            "autotune_gain": g_ms_h / g_ms, "autotuned_classes": len(classes)}
+            "flop_per_launch": flops, "builtin_tiles_ms": g_ms_h,
+            "autotune_gain": g_ms_h / g_ms, "tile_budget": budget, "skin_sigma": skin}
     config = {"workload": f"batch of {len(members)} LJ paths, atoms in {{108..2048}}, "
                           f"steps {min(m.n_steps for m in members)}..{max(m.n_steps for m in members)}, "
                           f"one persistent launch, graph-captured; input: {args.input}",

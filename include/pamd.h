@@ -72,13 +72,14 @@ extern "C" {
 
 /* ---- force precision (pamd_path.precision) ---- */
 #define PAMD_FP64 0               /* all arithmetic in float64 */
-#define PAMD_FP32_FORCE 1         /* LJ pair products in float32: each pair's force fs d and
-                                     Hessian-vector term a w + b (d.w) d is rounded to float32
-                                     before it is summed; displacements, cutoff test, the pair
-                                     functions of Eq. 16 (whose r^-12 powers would amplify float32
-                                     rounding twelvefold), the sums, residuals, actions and
-                                     gradients stay float64.  Gradient within 1e-8 of the float64
-                                     result.  Harmonic paths ignore this. */
+#define PAMD_FP32_FORCE 1         /* LJ pair products of the Hessian-vector pass in float32: each
+                                     pair's term a w + b (d.w) d is formed in float32 before it is
+                                     summed in float64.  The pair functions of Eq. 16 (whose r^-12
+                                     powers would amplify float32 rounding twelvefold), the force
+                                     pass, displacements, cutoff test, sums, residuals, actions and
+                                     gradients stay float64, so the action equals the float64 one
+                                     and the gradient is within 1e-8 of it.  Harmonic paths ignore
+                                     this. */
 
 /* ---- algorithm choice (pamd_tuning.algo) ---- */
 #define PAMD_ALGO_AUTO 0          /* fused */
@@ -246,9 +247,9 @@ const char* pamd_version(void);
  * harmonic member (Eq. 4 evaluated for each path, as pamd_action_grad does
  * for one).  The work list holds every (path, time tile) pair, largest first;
  * workgroups take items from it until it is empty.  All members must share
- * one precision.  Each Lennard-Jones member takes its tile and list skin from
- * the autotune cache when pamd_autotune has stored an entry for its problem
- * class (see below), else from a built-in rule.
+ * one precision.  Each Lennard-Jones member's time tile holds about the same
+ * work (tile = 16384 / n_atoms steps, within [4, 64], by default); the batch
+ * autotuner below picks that budget and the list skin by timing the launch.
  *
  * Two forms:
  *   - pamd_batch_action_grad: the paths' own device buffers, passed as host
@@ -298,6 +299,20 @@ int pamd_batch_layout(const pamd_batch* batch, int64_t* x_offsets, int64_t* step
  * outside any graph capture; the workspace then stays valid for any number of
  * calls on this batch. */
 int pamd_batch_prepare(const pamd_batch* batch, void* ws, size_t ws_bytes, void* stream);
+
+/* Batch autotuning: times the prepared launch (pamd_batch_run on x_all, with
+ * gradients into grad_all, which may be NULL) for each candidate member-tile
+ * policy (tile = budget / n_atoms steps for budgets 2^12 .. 2^16 atom-steps,
+ * list skin 0.3 or 0.5 sigma; fields the batch's tuning fixes are kept) and
+ * re-plans the batch with the fastest; when it fits `ws`, also prepares it
+ * (else call pamd_batch_layout for the new size and pamd_batch_prepare).
+ * Candidates whose workspace exceeds ws_bytes are skipped;
+ * pamd_batch_autotune_workspace_size gives the size that admits them all.
+ * Synchronises the stream; not capturable.  tile_budget and skin_frac (host,
+ * may be NULL) receive the choice. */
+int pamd_batch_autotune_workspace_size(pamd_batch* batch, size_t* bytes);
+int pamd_batch_autotune(pamd_batch* batch, const double* x_all, double* grad_all, void* ws,
+                        size_t ws_bytes, void* stream, double* tile_budget, double* skin_frac);
 
 /* Actions (and gradients) of every member of a prepared batch.
  *   x_all        device, packed paths

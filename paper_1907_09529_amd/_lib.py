@@ -91,6 +91,9 @@ _SIGNATURES = {
     "pamd_batch_run": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                                  c_void_p, c_void_p, c_size_t, c_void_p]),
     "pamd_batch_workspace_size": (c_int32, [c_int32, _PATH, _POT, POINTER(c_size_t)]),
+    "pamd_batch_autotune_workspace_size": (c_int32, [c_void_p, POINTER(c_size_t)]),
+    "pamd_batch_autotune": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p,
+                                      POINTER(c_double), POINTER(c_double)]),
     "pamd_batch_action_grad": (c_int32, [c_int32, _PATH, _POT, POINTER(c_void_p), c_void_p,
                                          POINTER(c_void_p), c_void_p, c_size_t, c_void_p]),
     "pamd_mh_workspace_size": (c_int32, [_PATH, _POT, _TUNE, POINTER(c_size_t)]),

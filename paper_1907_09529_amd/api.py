@@ -360,6 +360,24 @@ class PamdBatch:
         self.ws = ws
         return ws
 
+    def autotune(self, x_all, grad_all=None, stream=None):
+        """Times the member-tile policies on x_all, keeps the fastest and
+        prepares the batch for it; returns (tile budget, skin in sigma)."""
+        nb = ctypes.c_size_t(0)
+        _call("pamd_batch_autotune_workspace_size", self._h, ctypes.byref(nb))
+        ws = workspace(int(nb.value))
+        budget, skin = ctypes.c_double(0.0), ctypes.c_double(0.0)
+        nx = self.x_offsets[-1]
+        _call("pamd_batch_autotune", self._h, _ptr(x_all, name="x_all", numel=nx),
+              _ptr(grad_all, name="grad_all", numel=nx), _ptr(ws, None, "ws"),
+              ctypes.c_size_t(ws.numel()), _stream(stream), ctypes.byref(budget),
+              ctypes.byref(skin))
+        n = ctypes.c_size_t(0)
+        _call("pamd_batch_layout", self._h, None, None, ctypes.byref(n))
+        self.ws_bytes = int(n.value)
+        self.ws = ws
+        return budget.value, skin.value
+
     def pamd_batch_run(self, x_all, actions, grad_all=None, per_step_all=None,
                        weights_all=None, stream=None):
         if self.ws is None:

@@ -426,10 +426,6 @@ int evaluate(const pamd_path* p, const pamd_potential* v, const Plan& P, const d
 
 namespace pamd {
 
-bool tuning_from_cache(const pamd_path* p, const pamd_potential* v, pamd_tuning* out) {
-  return cached_tuning(p, v, out);
-}
-
 CellGrid choose_cells(double box, double radius, int n_atoms, int max_cells) {
   CellGrid g;
   const double rho = n_atoms / (box * box * box);

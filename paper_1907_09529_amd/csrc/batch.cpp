@@ -50,48 +50,31 @@ struct pamd_batch {
   FusedLaunch launch{};
   BlockScratch scratch_proto{};
   bool f32 = false;
+  // planning inputs: the caller's tuning (if any) and the member-tile policy
+  // (tile = tile_budget / n_atoms steps, clamped to [4, 64]; skin =
+  // skin_frac sigma unless the tuning fixes them)
+  bool has_tuning = false;
+  pamd_tuning tuning{};
+  double tile_budget = 16384.0;
+  double skin_frac = 0.5;
   // workspace offsets
+  size_t off_actions = 0;  // n_paths doubles: the autotuner's trial actions
   size_t off_members = 0, off_slots = 0, off_items = 0, off_counter = 0, off_steps = 0,
          off_bnd = 0, off_nbr = 0, off_cnt = 0, off_xref = 0, off_rglob = 0, total = 0;
   size_t nbr_stride = 0, cnt_stride = 0, xref_stride = 0, rglob_stride = 0;
 };
 
-extern "C" {
-
-int pamd_batch_create(int32_t n_paths, const pamd_path* paths, const pamd_potential* pots,
-                      const pamd_tuning* tuning, pamd_batch** out) {
-  if (!out) return batch_fail(PAMD_EINVAL, "out is NULL");
-  *out = nullptr;
-  if (n_paths < 1) return batch_fail(PAMD_EINVAL, "n_paths must be >= 1");
-  if (!paths || !pots) return batch_fail(PAMD_EINVAL, "paths and pots must be non-NULL");
-  if (tuning && tuning->algo == PAMD_ALGO_PLAIN)
-    return batch_fail(PAMD_EUNSUPPORTED, "batches run the fused form only");
-  for (int p = 0; p < n_paths; ++p) {
-    size_t dummy;
-    int rc = pamd_workspace_size(&paths[p], &pots[p], tuning, &dummy);
-    if (rc) return rc;
-    if (paths[p].precision != paths[0].precision)
-      return batch_fail(PAMD_EUNSUPPORTED, "all batch members must share one precision");
-    if (paths[p].n_steps > (int64_t)INT32_MAX * 16)
-      return batch_fail(PAMD_EUNSUPPORTED, "member %d has too many steps for a batch", p);
-  }
-  pamd_batch* b = new pamd_batch;
-  b->paths.assign(paths, paths + n_paths);
-  b->pots.assign(pots, pots + n_paths);
-  b->f32 = paths[0].precision == PAMD_FP32_FORCE;
-  b->x_off.resize(n_paths + 1);
-  b->step_off.resize(n_paths + 1);
-  int64_t xo = 0, so = 0;
-  for (int p = 0; p < n_paths; ++p) {
-    b->x_off[p] = xo;
-    b->step_off[p] = so;
-    xo += (int64_t)align_up((size_t)((paths[p].n_steps + 1) * paths[p].n_dim * paths[p].n_atoms), 32);
-    so += (int64_t)align_up((size_t)paths[p].n_steps, 32);
-    (pots[p].kind == PAMD_LJ ? b->lj_ids : b->ho_ids).push_back(p);
-  }
-  b->x_off[n_paths] = xo;
-  b->step_off[n_paths] = so;
-
+namespace {
+// Plans the members' tiles and lists, the work list, the launch shape and the
+// workspace layout from b's paths, tuning and tile policy (replaces any
+// earlier plan).
+int plan_batch(pamd_batch* b) {
+  const pamd_tuning* tuning = b->has_tuning ? &b->tuning : nullptr;
+  b->members.clear();
+  b->slots.clear();
+  b->items.clear();
+  b->max_tiles = 1;
+  b->launch = FusedLaunch{};
   // Lennard-Jones members: per-member tiles and lists, batch-wide launch shape.
   int max_n = 1;
   size_t max_nbr = 0;
@@ -99,14 +82,10 @@ int pamd_batch_create(int32_t n_paths, const pamd_path* paths, const pamd_potent
   int64_t bnd_elems = 0;
   const double skin_in = tuning && tuning->skin > 0 ? tuning->skin : -1.0;
   for (int p : b->lj_ids) {
-    const pamd_path& P = paths[p];
-    const pamd_potential& V = pots[p];
+    const pamd_path& P = b->paths[p];
+    const pamd_potential& V = b->pots[p];
     const int N = P.n_atoms;
-    // an autotuned single-path launch of the same problem class (pamd_autotune)
-    // gives the member its tile and skin; otherwise the built-in heuristic
-    pamd_tuning tuned{};
-    const bool have = tuning_from_cache(&P, &V, &tuned);
-    const double skin = skin_in > 0 ? skin_in : (have && tuned.skin > 0 ? tuned.skin : 0.5 * V.sigma);
+    const double skin = skin_in > 0 ? skin_in : b->skin_frac * V.sigma;
     const double radius = V.rc + skin;
     radii.push_back(radius);
     const double rho = N / (V.box * V.box * V.box);
@@ -116,9 +95,7 @@ int pamd_batch_create(int32_t n_paths, const pamd_path* paths, const pamd_potent
     kmax = (int)align_up((size_t)kmax, 8);  // lists are read in chunks of 8
     int tile = tuning && tuning->tile > 0
                    ? tuning->tile
-                   : (have && tuned.tile > 0
-                          ? tuned.tile
-                          : (int)std::max(4, std::min(64, (int)std::ceil(16384.0 / N))));
+                   : (int)std::max(4.0, std::min(64.0, std::ceil(b->tile_budget / N)));
     tile = (int)std::min<int64_t>(tile, P.n_steps);
     BatchMember m;
     std::memset(&m, 0, sizeof(m));
@@ -183,7 +160,6 @@ int pamd_batch_create(int32_t n_paths, const pamd_path* paths, const pamd_potent
     L.block = std::max(64, std::min(1024, block));
     L.half = list == PAMD_LIST_HALF;  // automatic choice: full lists
     if (L.half && max_n > fused_half_slots() * L.block) {
-      delete b;
       return batch_fail(PAMD_EUNSUPPORTED, "half lists do not fit this batch");
     }
     // one residual placement for the whole batch: in LDS with two slot
@@ -209,7 +185,6 @@ int pamd_batch_create(int32_t n_paths, const pamd_path* paths, const pamd_potent
       return true;
     };
     if (!fit_all(true, true) && !fit_all(true, false) && !fit_all(false, false)) {
-      delete b;
       return batch_fail(PAMD_EUNSUPPORTED, "batch member with %d atoms exceeds LDS", max_n);
     }
     L.grid = std::max(1, std::min<int>((int)b->items.size(), kMaxGrid));
@@ -223,7 +198,8 @@ int pamd_batch_create(int32_t n_paths, const pamd_path* paths, const pamd_potent
   b->off_slots = bump(cur, sizeof(int32_t) * std::max<size_t>(1, b->slots.size()));
   b->off_items = bump(cur, sizeof(BatchItem) * std::max<size_t>(1, b->items.size()));
   b->off_counter = bump(cur, sizeof(int32_t));
-  b->off_steps = bump(cur, sizeof(double) * (size_t)so);
+  b->off_steps = bump(cur, sizeof(double) * (size_t)b->step_off.back());
+  b->off_actions = bump(cur, sizeof(double) * b->paths.size());
   b->off_bnd = bump(cur, sizeof(double) * (size_t)bnd_elems);
   const size_t G = b->lj_ids.empty() ? 0 : (size_t)L.grid;
   b->off_nbr = bump(cur, sizeof(uint16_t) * b->nbr_stride * G);
@@ -231,6 +207,55 @@ int pamd_batch_create(int32_t n_paths, const pamd_path* paths, const pamd_potent
   b->off_xref = bump(cur, sizeof(double) * b->xref_stride * G);
   b->off_rglob = bump(cur, sizeof(double) * b->rglob_stride * G);
   b->total = align_up(cur, kAlign);
+  return PAMD_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int pamd_batch_create(int32_t n_paths, const pamd_path* paths, const pamd_potential* pots,
+                      const pamd_tuning* tuning, pamd_batch** out) {
+  if (!out) return batch_fail(PAMD_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (n_paths < 1) return batch_fail(PAMD_EINVAL, "n_paths must be >= 1");
+  if (!paths || !pots) return batch_fail(PAMD_EINVAL, "paths and pots must be non-NULL");
+  if (tuning && tuning->algo == PAMD_ALGO_PLAIN)
+    return batch_fail(PAMD_EUNSUPPORTED, "batches run the fused form only");
+  for (int p = 0; p < n_paths; ++p) {
+    size_t dummy;
+    int rc = pamd_workspace_size(&paths[p], &pots[p], tuning, &dummy);
+    if (rc) return rc;
+    if (paths[p].precision != paths[0].precision)
+      return batch_fail(PAMD_EUNSUPPORTED, "all batch members must share one precision");
+    if (paths[p].n_steps > (int64_t)INT32_MAX * 16)
+      return batch_fail(PAMD_EUNSUPPORTED, "member %d has too many steps for a batch", p);
+  }
+  pamd_batch* b = new pamd_batch;
+  b->paths.assign(paths, paths + n_paths);
+  b->pots.assign(pots, pots + n_paths);
+  b->f32 = paths[0].precision == PAMD_FP32_FORCE;
+  b->x_off.resize(n_paths + 1);
+  b->step_off.resize(n_paths + 1);
+  int64_t xo = 0, so = 0;
+  for (int p = 0; p < n_paths; ++p) {
+    b->x_off[p] = xo;
+    b->step_off[p] = so;
+    xo += (int64_t)align_up((size_t)((paths[p].n_steps + 1) * paths[p].n_dim * paths[p].n_atoms), 32);
+    so += (int64_t)align_up((size_t)paths[p].n_steps, 32);
+    (pots[p].kind == PAMD_LJ ? b->lj_ids : b->ho_ids).push_back(p);
+  }
+  b->x_off[n_paths] = xo;
+  b->step_off[n_paths] = so;
+
+  if (tuning) {
+    b->has_tuning = true;
+    b->tuning = *tuning;
+  }
+  int rc = plan_batch(b);
+  if (rc) {
+    delete b;
+    return rc;
+  }
   *out = b;
   return PAMD_OK;
 }
@@ -351,6 +376,106 @@ int pamd_batch_run(const pamd_batch* b, const double* x_all, const double* w_all
   if (rc) return rc;
   return run_batch(b, x_all, w_all, actions, per_step_all, grad_all, nullptr, nullptr, ws,
                    (hipStream_t)stream);
+}
+
+}  // extern "C"
+
+namespace {
+struct TilePolicy {
+  double budget, skin_frac;
+};
+// Member-tile policies the batch autotuner times: tile = budget / n_atoms
+// steps (so the tiles of all members hold similar work), and the list skin.
+std::vector<TilePolicy> batch_policies(const pamd_batch* b) {
+  const bool fixed_tile = b->has_tuning && b->tuning.tile > 0;
+  const bool fixed_skin = b->has_tuning && b->tuning.skin > 0;
+  std::vector<TilePolicy> out;
+  for (double budget : {4096.0, 8192.0, 16384.0, 32768.0, 65536.0}) {
+    if (fixed_tile && budget != 16384.0) continue;
+    for (double skin : {0.3, 0.5}) {
+      if (fixed_skin && skin != 0.5) continue;
+      out.push_back({budget, skin});
+    }
+  }
+  return out;
+}
+}  // namespace
+
+extern "C" {
+
+int pamd_batch_autotune_workspace_size(pamd_batch* b, size_t* bytes) {
+  if (!b || !bytes) return batch_fail(PAMD_EINVAL, "batch and bytes must be non-NULL");
+  const TilePolicy keep{b->tile_budget, b->skin_frac};
+  size_t need = b->total;
+  for (const TilePolicy& c : batch_policies(b)) {
+    b->tile_budget = c.budget;
+    b->skin_frac = c.skin_frac;
+    if (plan_batch(b) == PAMD_OK) need = std::max(need, b->total);
+  }
+  b->tile_budget = keep.budget;
+  b->skin_frac = keep.skin_frac;
+  int rc = plan_batch(b);
+  if (rc) return rc;
+  *bytes = need;
+  return PAMD_OK;
+}
+
+int pamd_batch_autotune(pamd_batch* b, const double* x_all, double* grad_all, void* ws,
+                        size_t ws_bytes, void* stream, double* tile_budget, double* skin_frac) {
+  if (!b) return batch_fail(PAMD_EINVAL, "batch is NULL");
+  if (!x_all) return batch_fail(PAMD_EINVAL, "x_all is NULL");
+  if (!ws || ((uintptr_t)ws) % kAlign) return batch_fail(PAMD_EWORKSPACE, "workspace must be non-NULL and 256-byte aligned");
+  hipStream_t st = (hipStream_t)stream;
+  double* actions = nullptr;  // the trial runs' actions (workspace)
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return batch_fail(PAMD_EHIP, "hipEventCreate failed");
+  if (hipEventCreate(&e1) != hipSuccess) {
+    hipEventDestroy(e0);
+    return batch_fail(PAMD_EHIP, "hipEventCreate failed");
+  }
+  TilePolicy best{b->tile_budget, b->skin_frac};
+  float best_ms = 1e30f;
+  int rc = PAMD_OK;
+  for (const TilePolicy& c : batch_policies(b)) {
+    b->tile_budget = c.budget;
+    b->skin_frac = c.skin_frac;
+    if (plan_batch(b) != PAMD_OK || b->total > ws_bytes) continue;
+    if ((rc = pamd_batch_prepare(b, ws, ws_bytes, stream))) break;
+    actions = (double*)((char*)ws + b->off_actions);
+    if ((rc = run_batch(b, x_all, nullptr, actions, nullptr, grad_all, nullptr, nullptr, ws, st)))
+      break;
+    float ms_min = 1e30f;
+    for (int rep = 0; rep < 2; ++rep) {
+      hipEventRecord(e0, st);
+      rc = run_batch(b, x_all, nullptr, actions, nullptr, grad_all, nullptr, nullptr, ws, st);
+      hipEventRecord(e1, st);
+      if (rc) break;
+      if (hipEventSynchronize(e1) != hipSuccess) {
+        rc = batch_fail(PAMD_EHIP, "hipEventSynchronize failed");
+        break;
+      }
+      float ms = 0.0f;
+      hipEventElapsedTime(&ms, e0, e1);
+      ms_min = std::min(ms_min, ms);
+    }
+    if (rc) break;
+    if (ms_min < best_ms) {
+      best_ms = ms_min;
+      best = c;
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  b->tile_budget = best.budget;
+  b->skin_frac = best.skin_frac;
+  int rc2 = plan_batch(b);
+  if (rc) return rc;
+  if (rc2) return rc2;
+  if (best_ms >= 1e30f) return batch_fail(PAMD_EWORKSPACE, "no tile policy fits the %zu-byte workspace", ws_bytes);
+  if (tile_budget) *tile_budget = best.budget;
+  if (skin_frac) *skin_frac = best.skin_frac;
+  if (b->total > ws_bytes) return PAMD_OK;  // the caller prepares a larger workspace
+  return pamd_batch_prepare(b, ws, ws_bytes, stream);
 }
 
 int pamd_batch_workspace_size(int32_t n_paths, const pamd_path* paths, const pamd_potential* pots,

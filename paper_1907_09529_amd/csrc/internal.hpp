@@ -137,9 +137,6 @@ struct BatchBase {
   int32_t pad0;
 };
 
-// The autotune cache entry for this problem, if pamd_autotune has stored one.
-bool tuning_from_cache(const pamd_path* p, const pamd_potential* v, pamd_tuning* out);
-
 // Shared memory of the fused kernel's workgroup (bytes).
 // With rho in LDS (r_in_lds) there are two slot arrays (two) or one.
 size_t fused_lds_bytes(int n_atoms, int nc, bool r_in_lds, bool half, int block, bool two = true);

@@ -608,16 +608,7 @@ __device__ __forceinline__ void pass1_part(const PathArgs& a, const TileLDS& L,
     const double ir2 = iru * iru;
     const double ir6 = ir2 * ir2 * ir2;
     const double fsl = fma(ir2 * ir6, fma(k.f12, ir6, -k.f6), k.duc * iru);
-    if constexpr (F32) {
-      // float32 pair product, float64 sum (pair function in float64)
-      const float f = (float)fsl;
-      px = (double)(f * (float)dx);
-      py = (double)(f * (float)dy);
-      pz = (double)(f * (float)dz);
-      fx += px;
-      fy += py;
-      fz += pz;
-    } else {
+    {  // the force pass is float64 in both precisions
       fx = fma(fsl, dx, fx);
       fy = fma(fsl, dy, fy);
       fz = fma(fsl, dz, fz);
@@ -715,12 +706,10 @@ __device__ __forceinline__ void pass2_part(const PathArgs& a, const TileLDS& L, 
     const double wx = rx - qtx, wy = ry - qty, wz = rz - qtz;
     if constexpr (F32) {
       // pair functions in float64 (as below), the products with w and d in
-      // float32, the sums in float64
-      double iru;
-      if constexpr (decltype(check)::value)
-        iru = ok ? rsqrt_nr(r2) : 0.0;
-      else
-        iru = rsqrt_nr(fmax(r2, 1e-30));
+      // float32, the sums in float64.  Padding entries are masked: their
+      // clamped r^2 gives pair scalars that overflow float32, and inf * 0 is
+      // not 0.
+      const double iru = ok ? rsqrt_nr(fmax(r2, 1e-30)) : 0.0;
       const double ir2 = iru * iru;
       const double ir6 = ir2 * ir2 * ir2;
       const double ir8 = ir2 * ir6;

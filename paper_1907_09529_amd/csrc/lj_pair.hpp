@@ -54,20 +54,16 @@ struct PairMath<false> {
 
 template <>
 struct PairMath<true> {
-  // Float32 pair products: the pair functions (r^-2, the r^-6 / r^-12 chain,
-  // U'/r, U'') stay in float64, since their powers amplify float32 rounding
-  // about twelvefold; the products of the pair scalars with the displacement
-  // and with w (fs d, and a w + b (d.w) d) are formed in float32 and summed
-  // in float64.
+  // Float32 pair products in the Hessian-vector pass: the pair functions
+  // (r^-2, the r^-6 / r^-12 chain, U'/r, U'') stay in float64, since their
+  // powers amplify float32 rounding about twelvefold, and the products of the
+  // pair scalars with w and d (a w + b (d.w) d) are formed in float32 and
+  // summed in float64.  The force pass stays float64: its products, rounded
+  // to float32, alone move the gradient by ~1.7e-8 of its largest entry.
   static __device__ __forceinline__ void accum_force(const LJConst& lj, double dx, double dy,
                                                      double dz, double r2, double& fx,
                                                      double& fy, double& fz) {
-    double fs, ir2, sr6;
-    PairMath<false>::force(lj, r2, fs, ir2, sr6);
-    const float f = (float)fs;
-    fx += (double)(f * (float)dx);
-    fy += (double)(f * (float)dy);
-    fz += (double)(f * (float)dz);
+    PairMath<false>::accum_force(lj, dx, dy, dz, r2, fx, fy, fz);
   }
   static __device__ __forceinline__ void accum_hv(const LJConst& lj, double dx, double dy,
                                                   double dz, double r2, double wx, double wy,

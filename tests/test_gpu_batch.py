@@ -71,6 +71,27 @@ def test_pointer_array_form_vs_oracle(device):
     assert torch.allclose(act, act2, rtol=1e-13, atol=0.0)
 
 
+def test_batch_autotune_keeps_results(device):
+    """After pamd_batch_autotune re-plans the member tiles, the batch still
+    matches the oracle."""
+    members = [em_input("lj108", n_steps=40), em_input("lj108", n_atoms=256, n_steps=13),
+               em_input("lj27", n_steps=21), em_input("ho1d", n_steps=50)]
+    paths, pots = zip(*(lib_descriptors(w) for w, _ in members))
+    b = P.PamdBatch(list(paths), list(pots))
+    x = pack(b, [X for _, X in members])
+    grad = torch.zeros_like(x)
+    budget, skin = b.autotune(x, grad)
+    assert budget in (4096, 8192, 16384, 32768, 65536) and skin in (0.3, 0.5)
+    act = torch.empty(len(members), dtype=torch.float64, device="cuda")
+    grad.zero_()
+    b.pamd_batch_run(x, act, grad_all=grad)
+    torch.cuda.synchronize()
+    for p, (w, X) in enumerate(members):
+        s_ref, g_ref = oracle_full(w, X)
+        assert rel(float(act[p]), math.fsum(s_ref.tolist())) <= 1e-12, p
+        assert rel_inf(b.view(grad, p).cpu().numpy(), g_ref) <= 1e-10, p
+
+
 def test_batch64_full_workload(device):
     """The 64-path workload: every member against the single-path call, sampled
     slices of three members against the oracle."""
