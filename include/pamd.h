@@ -248,7 +248,7 @@ const char* pamd_version(void);
  * for one).  The work list holds every (path, time tile) pair, largest first;
  * workgroups take items from it until it is empty.  All members must share
  * one precision.  Each Lennard-Jones member's time tile holds about the same
- * work (tile = 16384 / n_atoms steps, within [4, 64], by default); the batch
+ * work (tile = 16384 / n_atoms steps, within [4, 128], by default); the batch
  * autotuner below picks that budget and the list skin by timing the launch.
  *
  * Two forms:
@@ -302,7 +302,8 @@ int pamd_batch_prepare(const pamd_batch* batch, void* ws, size_t ws_bytes, void*
 
 /* Batch autotuning: times the prepared launch (pamd_batch_run on x_all, with
  * gradients into grad_all, which may be NULL) for each candidate member-tile
- * policy (tile = budget / n_atoms steps for budgets 2^12 .. 2^16 atom-steps,
+ * policy (tile = budget / n_atoms steps, within [4, 128], for budgets 2^13 ..
+ * 2^18 atom-steps,
  * list skin 0.3 or 0.5 sigma; fields the batch's tuning fixes are kept) and
  * re-plans the batch with the fastest; when it fits `ws`, also prepares it
  * (else call pamd_batch_layout for the new size and pamd_batch_prepare).

@@ -51,7 +51,7 @@ struct pamd_batch {
   BlockScratch scratch_proto{};
   bool f32 = false;
   // planning inputs: the caller's tuning (if any) and the member-tile policy
-  // (tile = tile_budget / n_atoms steps, clamped to [4, 64]; skin =
+  // (tile = tile_budget / n_atoms steps, clamped to [4, 128]; skin =
   // skin_frac sigma unless the tuning fixes them)
   bool has_tuning = false;
   pamd_tuning tuning{};
@@ -95,7 +95,7 @@ int plan_batch(pamd_batch* b) {
     kmax = (int)align_up((size_t)kmax, 8);  // lists are read in chunks of 8
     int tile = tuning && tuning->tile > 0
                    ? tuning->tile
-                   : (int)std::max(4.0, std::min(64.0, std::ceil(b->tile_budget / N)));
+                   : (int)std::max(4.0, std::min(128.0, std::ceil(b->tile_budget / N)));
     tile = (int)std::min<int64_t>(tile, P.n_steps);
     BatchMember m;
     std::memset(&m, 0, sizeof(m));
@@ -390,7 +390,7 @@ std::vector<TilePolicy> batch_policies(const pamd_batch* b) {
   const bool fixed_tile = b->has_tuning && b->tuning.tile > 0;
   const bool fixed_skin = b->has_tuning && b->tuning.skin > 0;
   std::vector<TilePolicy> out;
-  for (double budget : {4096.0, 8192.0, 16384.0, 32768.0, 65536.0}) {
+  for (double budget : {8192.0, 16384.0, 32768.0, 65536.0, 131072.0, 262144.0}) {
     if (fixed_tile && budget != 16384.0) continue;
     for (double skin : {0.3, 0.5}) {
       if (fixed_skin && skin != 0.5) continue;
