@@ -372,10 +372,13 @@ def bench_path(args, w) -> int:
     print(f"[bench] warmup {args.warmup} steps, variant {args.variant}", file=sys.stderr, flush=True)
     ms_per_step, k_ms = _time_calls(step, args.warmup, args.steps, lib, torch)
     if args.copy_probe_mb:
+        # counter calibration: an elementwise kernel over the whole device
+        # that reads and writes copy_probe_mb MiB each (dst = src + 1)
         n = args.copy_probe_mb * (1 << 20) // 8
         src = torch.ones(n, dtype=torch.float64, device=dev)
         dst = torch.empty_like(src)
-        dst.copy_(src)
+        torch.cuda.synchronize()
+        torch.add(src, 1.0, out=dst)
         torch.cuda.synchronize()
         del src, dst
     units = w.n_steps * w.n_atoms

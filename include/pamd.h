@@ -139,9 +139,12 @@ typedef struct pamd_path {
  *                  overflow falls back to a scan over all atoms (still exact)
  *   neighbour_list PAMD_LIST_* (fused); half lists need n_atoms <= 2 * block
  *   slot_arrays    LDS copies of the slice (fused): 2 = the next slice loads
- *                  into a second array while the current one is in use, 1 =
- *                  one array (less shared memory, so more workgroups fit on a
- *                  compute unit), 0 = the library's choice */
+ *                  into a second array while the current one is in use (the
+ *                  per-slice lists of partners within r_c then live in device
+ *                  memory), 1 = one array, which leaves room to keep those
+ *                  lists in LDS when n_atoms <= block (else less shared memory
+ *                  per workgroup), 0 = the library's choice (1 where the lists
+ *                  fit in LDS, else 2) */
 typedef struct pamd_tuning {
   int32_t algo;
   int32_t block;

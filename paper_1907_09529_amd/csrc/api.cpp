@@ -167,6 +167,7 @@ struct Plan {
   double skin = 0;
   bool r_in_lds = true;
   bool lds2 = true;  // with r_in_lds: two slot arrays
+  bool exl = false;  // exact lists in LDS (one slot array)
   bool half = false;
   size_t lds = 0;
   // plain LJ
@@ -230,7 +231,21 @@ int make_plan(const pamd_path* p, const pamd_potential* v, const pamd_tuning* t_
     // asked for), else with one, else in global scratch
     const int slots = t.slot_arrays ? t.slot_arrays
                                     : (have_cache && cached.slot_arrays ? cached.slot_arrays : 0);
-    if (slots != 1 && fused_cells_fit(L, radius, N, P.block, true, P.half, &P.cells, &P.lds, true)) {
+    // full lists with one slot per thread: the exact lists can live in LDS
+    // (one slot array) when they fit; that is the default
+    if (!P.half && slots != 2 && N <= P.block) {
+      const CellGrid g = choose_cells(L, radius, N, 1 << 30);
+      const size_t b = exl_lds_bytes(N, g.nc, P.block);
+      if (b <= kLdsMax) {
+        P.exl = true;
+        P.cells = g;
+        P.lds = b;
+        P.r_in_lds = true;
+        P.lds2 = false;
+      }
+    }
+    if (P.exl) {
+    } else if (slots != 1 && fused_cells_fit(L, radius, N, P.block, true, P.half, &P.cells, &P.lds, true)) {
       P.r_in_lds = true;
       P.lds2 = true;
     } else if (fused_cells_fit(L, radius, N, P.block, true, P.half, &P.cells, &P.lds, false)) {
@@ -358,6 +373,7 @@ FusedLaunch launch_of(const Plan& P) {
   L.lds2 = P.lds2;
   L.f32 = P.f32;
   L.half = P.half;
+  L.exl = P.exl;
   L.lds_bytes = P.lds;
   return L;
 }
@@ -737,6 +753,11 @@ int em_plan(const pamd_path* p, const pamd_potential* v, const pamd_tuning* t, P
   pamd_path q = *p;
   q.n_steps = 1;
   if ((rc = make_plan(&q, v, t, false, P))) return rc;
+  if (P.exl) {  // the integrator keeps two slot arrays (its own kernel has no exact lists)
+    pamd_tuning t2 = t ? *t : pamd_tuning{};
+    t2.slot_arrays = 2;
+    if ((rc = make_plan(&q, v, &t2, false, P))) return rc;
+  }
   if (v->kind == PAMD_LJ) {
     if (P.algo != PAMD_ALGO_FUSED)
       return fail(PAMD_EUNSUPPORTED, "the integrator uses the fused force pass (algo PLAIN given)");
@@ -1022,7 +1043,6 @@ int pamd_autotune(const pamd_path* p, const pamd_potential* v, const double* x,
           blocks.push_back(b);
       for (int b : blocks)
         for (int slots : {2, 1}) {
-          if (slots == 1 && b > 512) continue;  // one array only pays when workgroups share a CU
           for (int tile : {4, 8, 16, 32})
             for (double skin : {0.2, 0.3, 0.45}) {
               pamd_tuning c{};

@@ -106,6 +106,7 @@ struct FusedLaunch {
   bool lds2;        // with r_in_lds: two slot arrays (else one)
   bool f32;
   bool half;        // half neighbour lists with LDS atomics (else full lists)
+  bool exl;         // exact lists in LDS, one slot array (lj_fused_exl_kernel)
   size_t lds_bytes;
 };
 
@@ -141,6 +142,8 @@ struct BatchBase {
 // With rho in LDS (r_in_lds) there are two slot arrays (two) or one.
 size_t fused_lds_bytes(int n_atoms, int nc, bool r_in_lds, bool half, int block, bool two = true);
 int fused_half_slots();
+// Shared memory of the exact-lists-in-LDS kernel (n_atoms <= block).
+size_t exl_lds_bytes(int n_atoms, int nc, int block);
 constexpr size_t kFusedLdsMax = 163840;  // LDS per workgroup on gfx950
 
 // Cell grid of a list build: nc cells per axis (0: all pairs), stencil

@@ -1097,6 +1097,423 @@ __device__ __forceinline__ TileScratch block_scratch(const BlockScratch& s) {
   return t;
 }
 
+// ===========================================================================
+// Exact lists in LDS.  The partners found within r_c in pass 1 are kept in
+// shared memory (EXL_CAP entries per half-row; entries beyond EXL_KEEP spill
+// to the half-row's global row, which is rare), so no per-slice list traffic
+// reaches device memory.  The slice has one slot array (position and rho),
+// and the next slice is fetched into registers during pass 2 and stored
+// after it.  Before pass 2 the two lanes of an atom even out their exact
+// rows, so that a wave's pass 2 runs about as long as its atoms' mean.  The
+// candidate rows are walked four entries at a time.
+// ===========================================================================
+constexpr int EXL_CAP = 32;             // LDS entries per half-row
+constexpr int EXL_KEEP = EXL_CAP - 1;   // entries kept in LDS; index EXL_KEEP is scratch
+
+size_t exl_lds_bytes(int n_atoms, int nc, int block) {
+  const size_t ncell = (size_t)nc * nc * nc;
+  size_t b = sizeof(double) * (size_t)n_atoms * XS_R;
+  b += sizeof(double) * 32 + sizeof(int) * 18 + 6 * (size_t)n_atoms + 16;
+  const size_t rows = (size_t)2 * n_atoms * EXL_CAP * sizeof(uint16_t);
+  return b + std::max<size_t>(rows, lds_shared_region(n_atoms, (int)ncell, block));
+}
+
+
+// Entries of row `row` of a list stored in chunks of 8 (entry k at
+// [(k / 8) rows + row] 8 + k % 8), visited four at a time with PF quarter
+// chunks in flight; entries past cnt are passed with valid = false.
+template <typename Pair>
+__device__ __forceinline__ void for_each_listed4(const uint16_t* list, int rows, int row, int cnt,
+                                                 Pair&& pair) {
+  constexpr int PF = 3;
+  const uint2* nb = reinterpret_cast<const uint2*>(list);
+  auto at = [&](int q) { return ((size_t)(q >> 1) * rows + row) * 2 + (q & 1); };
+  const int nq = (cnt + 3) >> 2;
+  uint2 buf[PF];
+#pragma unroll
+  for (int i = 0; i < PF; ++i) buf[i] = i < nq ? nb[at(i)] : make_uint2(0u, 0u);
+  for (int q = 0; q < nq; ++q) {
+    const uint2 cur = buf[0];
+#pragma unroll
+    for (int i = 0; i + 1 < PF; ++i) buf[i] = buf[i + 1];
+    buf[PF - 1] = q + PF < nq ? nb[at(q + PF)] : cur;
+    const int left = cnt - 4 * q;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) pair(ChunkOf<4>::entry(cur, e), e < left);
+  }
+}
+
+// Pass 1 of slot s, part `part`: force from candidate row 2 s + part, with
+// the partners within r_c appended to `row` (LDS) and, past EXL_KEEP, to
+// `spill` (global).  Returns their number, or -1 after an overflow scan
+// (then nothing is recorded).
+template <bool REC>
+__device__ __forceinline__ int pass1_exl(const PathArgs& a, const TileLDS& L, const TileScratch& ts,
+                                         int s, int part, lds_u16* row, uint16_t* spill,
+                                         double& fx, double& fy, double& fz) {
+  const BoxUnits& k = a.bu;
+  const int N = a.n_atoms;
+  const int ps = L.pos(s);
+  const double xs = L.X[XS_R * ps], ys = L.X[XS_R * ps + 1], zs = L.X[XS_R * ps + 2];
+  fx = fy = fz = 0.0;
+  uint32_t acc = 0;
+  auto body = [&](int t, bool valid, auto record) {
+    const f64x2 uxy = lds_ld2(L.X + XS_R * t);
+    const double dx = wrap_u(xs - uxy.x);
+    const double dy = wrap_u(ys - uxy.y);
+    const double dz = wrap_u(zs - L.X[XS_R * t + 2]);
+    const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+    const bool ok = valid && r2 <= k.rc2;
+    if constexpr (decltype(record)::value) {
+      row[min(acc, (uint32_t)EXL_KEEP)] = (uint16_t)t;
+      if (ok && acc >= (uint32_t)EXL_KEEP) spill[acc - EXL_KEEP] = (uint16_t)t;
+      acc += ok ? 1u : 0u;
+    }
+    double iru = rsqrt_nr(r2);
+    iru = ok ? iru : 0.0;
+    const double ir2 = iru * iru;
+    const double ir6 = ir2 * ir2 * ir2;
+    const double fsl = fma(ir2 * ir6, fma(k.f12, ir6, -k.f6), k.duc * iru);
+    fx = fma(fsl, dx, fx);
+    fy = fma(fsl, dy, fy);
+    fz = fma(fsl, dz, fz);
+  };
+  const int cnt = ts.cnt[2 * s + part];
+  if (cnt >= 0) {
+    for_each_listed4(ts.nbr, 2 * N, 2 * s + part, cnt, [&](int t, bool valid) {
+      body(t, valid, std::integral_constant<bool, REC>{});
+    });
+    return (int)acc;
+  }
+  for_each_atom<false, 2>(a, L, ts, s, part,
+                          [&](int t, bool valid) { body(t, valid, std::false_type{}); });
+  return -1;
+}
+
+// Pass 2 of slot s, part `part`: q_s from the exact row (LDS entries, then
+// the spilled tail), or from the part's share of an overflow scan (ec < 0).
+// Rows are padded with the slot itself to whole chunks of 4.
+template <bool F32>
+__device__ __forceinline__ void pass2_exl(const PathArgs& a, const TileLDS& L, const TileScratch& ts,
+                                          int s, int part, int ec, const lds_u16* row,
+                                          const uint16_t* spill, double& qx, double& qy,
+                                          double& qz) {
+  const BoxUnits& k = a.bu;
+  const int ps = L.pos(s);
+  const f64x2 o0 = lds_ld2(L.X + XS_R * ps), o1 = lds_ld2(L.X + XS_R * ps + 2),
+              o2 = lds_ld2(L.X + XS_R * ps + 4);
+  const double xs = o0.x, ys = o0.y, zs = o1.x, rx = o1.y, ry = o2.x, rz = o2.y;
+  qx = qy = qz = 0.0;
+  auto body = [&](int t, bool ok) {
+    const f64x2 a0 = lds_ld2(L.X + XS_R * t), a1 = lds_ld2(L.X + XS_R * t + 2),
+                a2 = lds_ld2(L.X + XS_R * t + 4);
+    const double dx = wrap_u(xs - a0.x);
+    const double dy = wrap_u(ys - a0.y);
+    const double dz = wrap_u(zs - a1.x);
+    const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+    const double wx = rx - a1.y, wy = ry - a2.x, wz = rz - a2.y;
+    if constexpr (F32) {
+      // pair functions float64, products with w and d float32, sums float64;
+      // the padding entries (r^2 = 0) are masked
+      const double iru = ok && r2 > 0.0 ? rsqrt_nr(r2) : 0.0;
+      const double ir2 = iru * iru;
+      const double ir6 = ir2 * ir2 * ir2;
+      const double ir8 = ir2 * ir6;
+      const double ducir = k.duc_L * iru;
+      const double fs = fma(ir8, fma(k.s12, ir6, -k.s6), ducir);
+      const double bv = fma(ir8, fma(k.b12, ir6, -k.b6), ducir) * ir2;
+      const float af = (float)(-fs);
+      const float tt = (float)(bv * fma(dx, wx, fma(dy, wy, dz * wz)));
+      qx += (double)fmaf(af, (float)wx, tt * (float)dx);
+      qy += (double)fmaf(af, (float)wy, tt * (float)dy);
+      qz += (double)fmaf(af, (float)wz, tt * (float)dz);
+    } else {
+      // padding entries name the slot itself (d = w = 0); clamping r^2 keeps
+      // their terms finite, so they add exactly 0; `ok` is false only in the
+      // overflow scan's cutoff test
+      double iru = rsqrt_nr(fmax(r2, 1e-30));
+      iru = ok ? iru : 0.0;
+      const double ir2 = iru * iru;
+      const double ir6 = ir2 * ir2 * ir2;
+      const double ir8 = ir2 * ir6;
+      const double ducir = k.duc_L * iru;
+      const double fs = fma(ir8, fma(k.s12, ir6, -k.s6), ducir);
+      const double bv = fma(ir8, fma(k.b12, ir6, -k.b6), ducir) * ir2;
+      const double tt = bv * fma(dx, wx, fma(dy, wy, dz * wz));
+      qx = fma(tt, dx, fma(-fs, wx, qx));
+      qy = fma(tt, dy, fma(-fs, wy, qy));
+      qz = fma(tt, dz, fma(-fs, wz, qz));
+    }
+  };
+  if (ec >= 0) {
+    typedef __attribute__((address_space(3))) unsigned long long lds_u64;
+    const int nq = ec > EXL_KEEP ? EXL_CAP / 4 : (ec + 3) >> 2;
+    for (int q = 0; q < nq; ++q) {
+      const unsigned long long v = *(const lds_u64*)(row + 4 * q);  // one 8-byte LDS read
+      const uint2 c = make_uint2((uint32_t)v, (uint32_t)(v >> 32));
+#pragma unroll
+      for (int e = 0; e < 4; ++e) body(ChunkOf<4>::entry(c, e), true);
+    }
+    if (ec > EXL_KEEP) {
+      const int nq2 = (ec - EXL_KEEP + 3) >> 2;
+      for (int q = 0; q < nq2; ++q) {
+        const uint2 c = reinterpret_cast<const uint2*>(spill)[q];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) body(ChunkOf<4>::entry(c, e), true);
+      }
+    }
+  } else {
+    for_each_atom<false, 2>(a, L, ts, s, part, [&](int t, bool) {
+      const double dx = wrap_u(xs - L.X[XS_R * t]);
+      const double dy = wrap_u(ys - L.X[XS_R * t + 1]);
+      const double dz = wrap_u(zs - L.X[XS_R * t + 2]);
+      body(t, fma(dx, dx, fma(dy, dy, dz * dz)) <= k.rc2);
+    });
+  }
+}
+
+// One tile with the exact lists in LDS (see above).  Full lists, rho in LDS,
+// one slot array; n_atoms <= blockDim.x (one slot per thread in the
+// next-slice fetch).
+template <bool F32, bool GRAD = true>
+__device__ void tile_body_exl(const PathArgs& a, int tile, const TileScratch& ts, char* lds_base) {
+  constexpr int XS = XS_R;
+  const int N = a.n_atoms;
+  const int ncell = a.nc * a.nc * a.nc;
+  TileLDS L = carve_lds(lds_base, N, ncell, true, false, false);
+  lds_u16* const EXR = L.stage;  // 2 N rows of EXL_CAP entries (shares the build's region)
+  const int64_t n0 = (int64_t)tile * a.tile;
+  const int64_t n1 = min(n0 + (int64_t)a.tile, a.n_steps);
+  const size_t slice = (size_t)3 * N;
+  const bool grad = GRAD && (a.mode & MODE_GRAD) != 0;
+  const bool excess = (a.mode & MODE_EXCESS) != 0;
+  const int B = blockDim.x;
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int part = lane >> 5;
+  const int wv = threadIdx.x / WAVE, nwv = B / WAVE;
+  const double box = a.lj.box, ib = a.lj.inv_box;
+  const int spill_stride = row_capacity<false>(a.kmax);  // entries per spilled half-row
+  double hs2 = a.bu.half_skin2, rl2 = a.bu.rlist2;
+
+  // Initial lists around each atom's centre over the tile (see tile_body);
+  // the per-atom reaches wait in global scratch.
+  double d2max = 0.0;
+  for (int i = threadIdx.x; i < N; i += B) {
+    L.perm[i] = (uint16_t)i;
+    double lo[3], hi[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      lo[c] = hi[c] = a.x[(size_t)n0 * slice + (size_t)c * N + i] * ib;
+      ts.rprev[3 * i + c] = 0.0;
+    }
+    for (int64_t m = n0 + 1; m < n1; ++m) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const double u = a.x[(size_t)m * slice + (size_t)c * N + i] * ib;
+        lo[c] = fmin(lo[c], u);
+        hi[c] = fmax(hi[c], u);
+      }
+    }
+    double di2 = 0.0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const double h = 0.5 * (hi[c] - lo[c]);
+      di2 = fma(h, h, di2);
+      L.X[XS * L.pos(i) + c] = 0.5 * (hi[c] + lo[c]);
+    }
+    ts.rglob[i] = di2;
+    d2max = fmax(d2max, di2);
+  }
+  if (threadIdx.x == 0) L.flag[0] = L.flag[1] = 0;
+  d2max = block_max_all(d2max, L.red) * (1.0 + 1e-10);
+  const double rcm = sqrt(a.bu.rc2) * (1.0 + 1e-12);
+  const double* reach = nullptr;
+  if (d2max <= hs2) {
+    hs2 = d2max;
+    const double r = sqrt(a.bu.rc2) + 2.0 * sqrt(d2max);
+    rl2 = r * r * (1.0 + 1e-12);
+    for (int i = threadIdx.x; i < N; i += B) ts.rglob[i] = sqrt(ts.rglob[i]) * (1.0 + 1e-12);
+    reach = ts.rglob;
+  }
+  const double reach_all = 0.5 * (sqrt(rl2) - rcm);
+  bool first = true;
+
+  // the next slice, fetched during pass 2 (slot threadIdx.x) and stored after it
+  double nx[3] = {0.0, 0.0, 0.0}, nref[3] = {0.0, 0.0, 0.0};
+  const int my = threadIdx.x;
+  auto store_next = [&](int64_t m) {
+    if (my < N) {
+      double d2 = 0.0;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const double u = nx[c] * ib;
+        L.X[XS * L.pos(my) + c] = u;
+        const double du = wrap_u(u - nref[c]);
+        d2 = fma(du, du, d2);
+      }
+      if (!(d2 <= hs2)) L.flag[m & 1] = 1;
+    }
+  };
+  auto fetch_next = [&](int64_t m) {
+    if (my < N) {
+      const int o = L.perm[my];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        nx[c] = a.x[(size_t)m * slice + (size_t)c * N + o];
+        nref[c] = ts.xref[3 * my + c];
+      }
+    }
+  };
+
+  for (int64_t n = n0; n < n1;) {
+    __syncthreads();  // X holds x_n (or the centres); flag[n & 1] is final
+    if (first || L.flag[n & 1]) {
+      rebuild<XS, false>(a, L, ts, rl2, rcm, first ? reach : nullptr, reach_all);
+      __syncthreads();  // lists and slots ready
+      if (first) {
+        first = false;
+        fetch_next(n0);
+        store_next(n0);
+        continue;
+      }
+    }
+    const double w = a.weights ? a.weights[n] : 1.0;
+    const double* xcur = a.x + (size_t)n * slice;
+    const double* xnext = xcur + slice;
+
+    // ---- pass 1: force, exact rows, residual, per-step action ----
+    double s_loc = 0.0, e_loc = 0.0;
+    for (int base = wv * 32; base < N; base += nwv * 32) {
+      const int s = base + (lane & 31);
+      const bool live = s < N;
+      const int r = 2 * (live ? s : 0) + part;
+      lds_u16* row = EXR + (size_t)r * EXL_CAP;
+      uint16_t* spill = ts.ex + (size_t)r * spill_stride;
+      double f[3] = {0.0, 0.0, 0.0};
+      int c = 0;
+      if (live) c = pass1_exl<GRAD>(a, L, ts, s, part, row, spill, f[0], f[1], f[2]);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) f[k] += __shfl_xor(f[k], 32, WAVE);
+      // even out the atom's two exact rows (both in LDS), then pad to whole chunks
+      const int co = __shfl_xor(c, 32, WAVE);
+      if (live && GRAD) {
+        if (c >= 0 && co >= 0 && c <= EXL_KEEP && co <= EXL_KEEP) {
+          const int E = c + co;
+          const int h = part == 0 ? (E + 1) >> 1 : E >> 1;
+          if (c > h) {
+            lds_u16* other = EXR + (size_t)(r ^ 1) * EXL_CAP;
+            for (int j = 0; j < c - h; ++j) other[co + j] = row[h + j];
+          }
+          c = h;
+        }
+        if (c >= 0) {
+          const uint16_t self = (uint16_t)L.pos(s);
+          if (c > EXL_KEEP) {
+            row[EXL_KEEP] = self;
+            for (int i = c - EXL_KEEP; i & 3; ++i) spill[i] = self;
+          } else {
+            for (int i = c; i & 3; ++i) row[i] = self;
+          }
+        }
+        L.ecnt[r] = (int16_t)c;
+      }
+      if (live && part == 0) {
+        const int o = L.perm[s];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          const size_t e = (size_t)k * N + o;
+          const double d = min_image(xnext[e] - xcur[e], box, ib);
+          const double rr = fma(-a.mu_dt, f[k], d);
+          s_loc = fma(rr, rr, s_loc);
+          e_loc = fma(rr - d, rr + d, e_loc);
+          if (grad) L.X[XS * L.pos(s) + 3 + k] = w * rr;
+        }
+      }
+    }
+    {
+      const double ws_ = wave_sum(s_loc);
+      const double we_ = excess ? wave_sum(e_loc) : 0.0;
+      if (lane == 0) {
+        L.red[wv] = ws_;
+        L.red[16 + wv] = we_;
+      }
+    }
+    __syncthreads();  // rho_n of every atom and every exact row are stored
+    if (threadIdx.x == 0) {
+      double t = 0.0;
+      for (int k = 0; k < nwv; ++k) t += L.red[k];
+      a.per_step[n] = t * a.inv4Ddt;
+      if (excess) {
+        double e = 0.0;
+        for (int k = 0; k < nwv; ++k) e += L.red[16 + k];
+        a.excess[n] = e * a.inv4Ddt;
+      }
+      L.flag[n & 1] = 0;
+    }
+    const bool more = n + 1 < n1;
+    if (more) fetch_next(n + 1);
+
+    // ---- pass 2: Hessian-vector product and gradient ----
+    if (grad) {
+      const double cq = a.c * a.mu_dt;
+      for (int base = wv * 32; base < N; base += nwv * 32) {
+        const int s = base + (lane & 31);
+        const bool live = s < N;
+        double q[3] = {0.0, 0.0, 0.0};
+        if (live) {
+          const int r = 2 * s + part;
+          pass2_exl<F32>(a, L, ts, s, part, L.ecnt[r], EXR + (size_t)r * EXL_CAP,
+                         ts.ex + (size_t)r * spill_stride, q[0], q[1], q[2]);
+        }
+#pragma unroll
+        for (int k = 0; k < 3; ++k) q[k] += __shfl_xor(q[k], 32, WAVE);
+        if (live && part == 0) {
+          const int o = L.perm[s];
+#pragma unroll
+          for (int k = 0; k < 3; ++k) {
+            const double rho = L.X[XS * L.pos(s) + 3 + k];
+            const double g = fma(cq, q[k], a.c * (ts.rprev[3 * o + k] - rho));
+            a.grad[(size_t)n * slice + (size_t)k * N + o] = g;
+            ts.rprev[3 * o + k] = rho;
+          }
+        }
+      }
+    }
+    __syncthreads();  // every read of slice n in X is done
+    if (more) store_next(n + 1);
+    ++n;
+  }
+
+  if (grad) {
+    __syncthreads();
+    for (int o = threadIdx.x; o < N; o += B) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const double v = a.c * ts.rprev[3 * o + c];
+        if (n1 == a.n_steps)
+          a.grad[(size_t)a.n_steps * slice + (size_t)c * N + o] = v;
+        else
+          a.bnd[(size_t)tile * slice + (size_t)c * N + o] = v;
+      }
+    }
+  }
+  __syncthreads();  // LDS is reused by the next tile of this block
+}
+
+template <bool F32>
+__global__ void __launch_bounds__(1024) lj_fused_exl_kernel(PathArgs a, BlockScratch s) {
+  extern __shared__ __align__(16) char lds[];
+  const TileScratch ts = block_scratch(s);
+  for (int t = blockIdx.x; t < a.n_tiles; t += gridDim.x) tile_body_exl<F32>(a, t, ts, lds);
+}
+
+template <bool F32>
+__global__ void __launch_bounds__(1024) lj_action_exl_kernel(PathArgs a, BlockScratch s) {
+  extern __shared__ __align__(16) char lds[];
+  const TileScratch ts = block_scratch(s);
+  for (int t = blockIdx.x; t < a.n_tiles; t += gridDim.x) tile_body_exl<F32, false>(a, t, ts, lds);
+}
+
 template <bool F32, bool RLDS, bool HALF>
 __global__ void __launch_bounds__(1024) lj_fused_kernel(PathArgs a, BlockScratch s) {
   extern __shared__ __align__(16) char lds[];
@@ -1308,6 +1725,18 @@ hipError_t launch_lj_em(const PathArgs& a, const double* xi, double amp, double*
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
+template <bool F32>
+static hipError_t launch_exl_t(const PathArgs& a, const BlockScratch& s, const FusedLaunch& L,
+                               hipStream_t st) {
+  auto kern = (a.mode & MODE_GRAD) ? lj_fused_exl_kernel<F32> : lj_action_exl_kernel<F32>;
+  hipError_t e = hipFuncSetAttribute((const void*)kern,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)L.lds_bytes);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(kern, dim3(L.grid), dim3(L.block), L.lds_bytes, st, a, s);
+  return hipGetLastError();
+}
+
 template <bool F32, bool RLDS, bool HALF>
 static hipError_t launch_fused_t(const PathArgs& a, const BlockScratch& s, const FusedLaunch& L,
                                  hipStream_t st) {
@@ -1348,6 +1777,7 @@ static hipError_t launch_batch_t(const BatchMember* m, const BatchBase& b, const
 
 hipError_t launch_lj_fused(const PathArgs& a, const BlockScratch& s, const FusedLaunch& L,
                            hipStream_t st) {
+  if (L.exl) return L.f32 ? launch_exl_t<true>(a, s, L, st) : launch_exl_t<false>(a, s, L, st);
   PAMD_DISPATCH(launch_fused_t, a, s, L, st)
 }
 

@@ -175,6 +175,28 @@ def test_lj864_em_ragged_tiles(device):
     check(w, X, precision="fp32_force", ref=ref)
 
 
+@pytest.mark.parametrize("rc", [2.6, 3.2])
+def test_lj500_long_exact_rows(device, rc):
+    """Cutoffs whose exact partner rows exceed what the workgroup keeps in
+    shared memory per half-row (the tail goes to device memory), with and
+    without the two halves of an atom evened out; against the oracle and the
+    form with the exact lists in device memory (two slot arrays)."""
+    import dataclasses
+    from oracle import em as OE
+    w = dataclasses.replace(W.workload("lj108").with_atoms(500).with_steps(12), rc=rc)
+    pot = oracle_pot(w)
+    xi, eta = W.draw_noise(w)
+    X = OE.perturbed_em_path(W.initial_lattice(w.n_atoms, w.box), xi, eta, w.perturb_sd, pot,
+                             w.dt, w.D, w.gamma)
+    ref = oracle_full(w, X)
+    path, lpot = lib_descriptors(w)
+    assert P.pamd_launch_info(path, lpot).lds_bytes > 0
+    check(w, X, ref=ref)
+    check(w, X, tuning=P.make_tuning("fused", slot_arrays=2), ref=ref)
+    check(w, X, tuning=P.make_tuning("fused", tile=3, skin=0.05), ref=ref)
+    check(w, X, precision="fp32_force", ref=ref)
+
+
 def test_lj500_cell_list_path(device):
     # 500 atoms: n_c = 3 cells of edge >= 2.8 (reach 1) or 5 with reach 2
     w, X = em_input("lj108", n_atoms=500, n_steps=24)
