@@ -54,22 +54,25 @@ RECOUNT_HV_PAIR = 59
 RECOUNT_SLICE_ATOM = 39
 BYTES_SLICE_ATOM = 48       # read x_n (24 B) + write g_n (24 B)
 
-# HBM bytes per launch of lj_fused_kernel on the default workload and tuning,
-# from rocprofv3 FETCH_SIZE / WRITE_SIZE runs scaled by a 512 MiB copy
-# (profiles/lj_fused_lj864x4096.md).  Reported only while the kernel sources
-# still hash to `sha`; any change to them makes `traffic` null until the
-# counters are taken again.
-MEASURED_TRAFFIC = {"sha": "ddefa2c5d4f307fc", "input": "tethered", "read_bytes": 1.5197e9,
-                    "write_bytes": 8.5405e8}
+# HBM bytes per launch of the default fused kernel (lj_fused_exl_kernel) on
+# the default workload, input and tuning, from rocprofv3 FETCH_SIZE /
+# WRITE_SIZE runs scaled by a 2 GiB elementwise kernel that reads and writes
+# known amounts (profiles/lj_fused_exl_lj864x4096.md).  Reported only while
+# the kernel sources still hash to `sha`; any change to them makes `traffic`
+# null until the counters are taken again.
+MEASURED_TRAFFIC = {"sha": "0405b9277341217f", "input": "em", "read_bytes": 1.06787e9,
+                    "write_bytes": 2.79580e8}
 # VALU instruction counters of the same kernel, input and tuning (per launch;
 # rocprofv3 --pmc, wave-level counts): the FP64 operations it issued, to set
 # beside the algorithmic fraction (they include candidates beyond the cutoff
 # and each pair's second evaluation from the partner's list).
-MEASURED_VALU = {"sha": "ddefa2c5d4f307fc", "input": "tethered", "valu": 4.5040e8,
-                 "fma_f64": 1.0297e8, "mul_f64": 8.0166e7, "add_f64": 7.6232e7,
-                 "trans_f64": 7.9844e6}
+MEASURED_VALU = {"sha": "0405b9277341217f", "input": "em", "valu": 4.30532e8,
+                 "fma_f64": 1.01863e8, "mul_f64": 7.86328e7, "add_f64": 7.53234e7,
+                 "trans_f64": 7.72362e6}
+# the kernel's sources and the planner that picks its launch
 TRAFFIC_SOURCES = ["paper_1907_09529_amd/csrc/lj_fused.hip", "paper_1907_09529_amd/csrc/device.hpp",
-                   "paper_1907_09529_amd/csrc/internal.hpp"]
+                   "paper_1907_09529_amd/csrc/internal.hpp", "paper_1907_09529_amd/csrc/lj_pair.hpp",
+                   "paper_1907_09529_amd/csrc/api.cpp", "include/pamd.h"]
 
 
 def kernel_sources_sha() -> str:
@@ -398,7 +401,8 @@ def bench_path(args, w) -> int:
     roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64_VALU / 1e12,
             "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VALU, "traffic": traffic,
             "traffic_unit": "bytes per launch (HBM read + write)",
-            "kernel": "lj_fused_kernel" if args.variant != "plain" else "plain pipeline",
+            "kernel": ("plain pipeline" if args.variant == "plain" else
+                       "lj_fused_exl_kernel" if launch.exact_lists else "lj_fused_kernel"),
             "kernel_ms": k_ms, "flop_per_slice_atom": flop_unit,
             "flop_constants": [FLOP_FORCE_PAIR, FLOP_HV_PAIR, FLOP_SLICE_ATOM],
             "pairs_per_atom": ppa,
@@ -439,7 +443,8 @@ def bench_path(args, w) -> int:
                           f"rc {w.cutoff:.4g}, dt {w.dt:g}, {args.variant}; input: {input_name}",
               "neighbour_list": args.list, "input": args.input,
               "n_atoms": w.n_atoms, "n_steps": w.n_steps, "variant": args.variant,
-              "tile": launch.tile, "block": launch.block, "parallelism": "single GPU"}
+              "tile": launch.tile, "block": launch.block, "slot_arrays": launch.slot_arrays,
+              "exact_lists": launch.exact_lists, "parallelism": "single GPU"}
     baseline = None
     if not args.no_cpu_baseline:
         host = x[:min(w.n_steps + 1, 4097)].cpu().numpy()
@@ -938,7 +943,9 @@ def bench_pamd(args, w) -> int:
     em_rate = w_e.dt / (em_step_ms * 1e-3)
     roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64_VALU / 1e12,
             "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VALU, "traffic": None,
-            "kernel": "lj_action_kernel (excess action of the trial path)", "kernel_ms": k_ms,
+            "kernel": ("lj_action_exl_kernel" if P.pamd_launch_info(path, pot).exact_lists
+                       else "lj_action_kernel") + " (excess action of the trial path)",
+            "kernel_ms": k_ms,
             "flop_per_slice_atom": flop_unit, "pairs_per_atom": ppa}
     config = {"workload": f"path-based integration, LJ {w.n_atoms} atoms, rho {w.density}, "
                           f"rc {w.cutoff:.4g}, N_path {n_path}, levels {SIM2['l_min']}.."
@@ -1013,13 +1020,16 @@ def bench_langevin(args, w, tau: float = 1e-7) -> int:
     k_ms = float(np.mean([e.elapsed_ms() for e in kev]))
     for e in kev:
         e.close()
-    ppa = pairs_per_atom(X, w.box, w.cutoff)
+    idx = torch.from_numpy(np.linspace(0, w.n_steps, 8).astype(int)).to(dev)
+    ppa = pairs_per_atom(y[idx].cpu().numpy(), w.box, w.cutoff)
     flop_unit = ppa * (FLOP_FORCE_PAIR + FLOP_HV_PAIR) + FLOP_SLICE_ATOM
     units = w.n_steps * w.n_atoms
     achieved = flop_unit * units / (k_ms * 1e-3)
+    kname = ("lj_fused_exl_kernel" if P.pamd_launch_info(path, pot).exact_lists
+             else "lj_fused_kernel")
     roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64_VALU / 1e12,
             "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VALU, "traffic": None,
-            "kernel": "lj_fused_kernel (action + gradient of the proposal)", "kernel_ms": k_ms,
+            "kernel": f"{kname} (action + gradient of the proposal)", "kernel_ms": k_ms,
             "flop_per_slice_atom": flop_unit, "pairs_per_atom": ppa}
     config = {"workload": f"gradient-informed path move, LJ {w.n_atoms} atoms x {w.n_steps} steps, "
                           f"tau {tau:g}, graph-replayed moves; start path: {input_name}",

@@ -176,6 +176,9 @@ typedef struct pamd_launch {
   int32_t max_neighbours;   /* list capacity per atom */
   int32_t neighbour_list;   /* PAMD_LIST_FULL or PAMD_LIST_HALF */
   int32_t lds_bytes;        /* shared memory per workgroup */
+  int32_t slot_arrays;      /* residual slot arrays in LDS: 1 or 2 (0: residuals in device memory) */
+  int32_t exact_lists;      /* 1: each atom's partners within the cutoff, found in the force
+                               pass, stay in LDS for the Hessian-vector pass (fused, full lists) */
   double skin;              /* list skin in length units */
 } pamd_launch;
 

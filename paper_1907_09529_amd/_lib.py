@@ -55,7 +55,7 @@ class PamdLaunch(ctypes.Structure):
     _fields_ = [("algo", c_int32), ("block", c_int32), ("tile", c_int32), ("n_tiles", c_int32),
                 ("grid", c_int32), ("cells", c_int32), ("reach", c_int32),
                 ("max_neighbours", c_int32), ("neighbour_list", c_int32), ("lds_bytes", c_int32),
-                ("skin", c_double)]
+                ("slot_arrays", c_int32), ("exact_lists", c_int32), ("skin", c_double)]
 
 
 class PamdError(RuntimeError):

@@ -549,6 +549,8 @@ int pamd_launch_info(const pamd_path* p, const pamd_potential* v, const pamd_tun
   out->max_neighbours = P.kmax;
   out->neighbour_list = P.half ? PAMD_LIST_HALF : PAMD_LIST_FULL;
   out->lds_bytes = (int32_t)P.lds;
+  out->slot_arrays = P.r_in_lds ? (P.lds2 ? 2 : 1) : 0;
+  out->exact_lists = P.exl ? 1 : 0;
   return PAMD_OK;
 }
 

@@ -344,6 +344,10 @@ def test_launch_info_reports_the_plan():
     assert info.block % 64 == 0 and 64 <= info.block <= 1024
     assert info.grid == min(info.n_tiles, 2048)
     assert info.neighbour_list == _lib.PAMD_LIST_FULL and info.skin > 0
+    # default: exact partner lists kept in LDS, with one residual slot array
+    assert info.exact_lists == 1 and info.slot_arrays == 1
+    two = P.pamd_launch_info(path, pot, P.make_tuning("fused", slot_arrays=2))
+    assert two.exact_lists == 0 and two.slot_arrays == 2 and two.lds_bytes > 0
     t = P.make_tuning("fused", tile=7)
     assert P.pamd_launch_info(path, pot, t).tile == 7
     assert P.pamd_launch_info(path, pot, P.make_tuning("plain")).algo == _lib.PAMD_ALGO_PLAIN
