@@ -416,9 +416,9 @@ def bench_path(args, w) -> int:
         roof["counter_fp64_frac"] = ops / (k_ms * 1e-3) / PEAK_FP64_VALU
         roof["counter_valu_insts"] = MEASURED_VALU["valu"]
     if args.variant == "fp32_force":
-        roof["note"] = ("float32 pair arithmetic: without packed float32 instructions (not "
-                        "used by this build) the vector float32 rate equals the float64 rate, "
-                        "so the same peak applies")
+        roof["note"] = ("float32 only in the Hessian-vector pass's pair products (a w + b (d.w) d); "
+                        "the pair functions, the force pass and all sums stay float64, so the "
+                        "float64 peak applies")
     plain = None
     if default_run and not args.no_plain:
         # the unfused form on the same input, and its agreement with the fused one

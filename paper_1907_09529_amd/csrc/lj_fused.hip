@@ -1099,22 +1099,25 @@ __device__ __forceinline__ TileScratch block_scratch(const BlockScratch& s) {
 
 // ===========================================================================
 // Exact lists in LDS.  The partners found within r_c in pass 1 are kept in
-// shared memory (EXL_CAP entries per half-row; entries beyond EXL_KEEP spill
-// to the half-row's global row, which is rare), so no per-slice list traffic
-// reaches device memory.  The slice has one slot array (position and rho),
-// and the next slice is fetched into registers during pass 2 and stored
-// after it.  Before pass 2 the two lanes of an atom even out their exact
-// rows, so that a wave's pass 2 runs about as long as its atoms' mean.  The
-// candidate rows are walked four entries at a time.
+// shared memory for pass 2, so no per-slice list traffic reaches device
+// memory.  Each atom owns EXL_ROW entries: the lane of part 0 appends its
+// partners from the front, the lane of part 1 from the back, so the region
+// overflows only when the atom has more than EXL_ROW partners in all (then
+// pass 2 walks the candidate rows again with the cutoff test).  Before
+// pass 2 the lane with more partners hands the ones nearest the gap to the
+// other lane, so both walk about half, each from its own end of the region
+// in whole chunks of four.  The slice has one slot array (position and rho),
+// and the next slice is fetched into registers during pass 2 and stored after
+// it.  The candidate rows are walked four entries at a time.
 // ===========================================================================
-constexpr int EXL_CAP = 32;             // LDS entries per half-row
-constexpr int EXL_KEEP = EXL_CAP - 1;   // entries kept in LDS; index EXL_KEEP is scratch
+constexpr int EXL_ROW = 64;  // LDS entries per atom (both parts)
 
 size_t exl_lds_bytes(int n_atoms, int nc, int block) {
   const size_t ncell = (size_t)nc * nc * nc;
   size_t b = sizeof(double) * (size_t)n_atoms * XS_R;
   b += sizeof(double) * 32 + sizeof(int) * 18 + 6 * (size_t)n_atoms + 16;
-  const size_t rows = (size_t)2 * n_atoms * EXL_CAP * sizeof(uint16_t);
+  // the atoms' regions, then one discard entry per thread
+  const size_t rows = ((size_t)n_atoms * EXL_ROW + (size_t)block) * sizeof(uint16_t);
   return b + std::max<size_t>(rows, lds_shared_region(n_atoms, (int)ncell, block));
 }
 
@@ -1144,17 +1147,20 @@ __device__ __forceinline__ void for_each_listed4(const uint16_t* list, int rows,
 }
 
 // Pass 1 of slot s, part `part`: force from candidate row 2 s + part, with
-// the partners within r_c appended to `row` (LDS) and, past EXL_KEEP, to
-// `spill` (global).  Returns their number, or -1 after an overflow scan
-// (then nothing is recorded).
+// the partners within r_c written to the atom's region `reg` (part 0 from
+// entry 0 upwards, part 1 from entry EXL_ROW - 1 downwards; a candidate that
+// is not kept goes to the lane's discard entry).  Returns their number (which
+// may exceed what the region holds), or -1 after an overflow scan (then
+// nothing is recorded).
 template <bool REC>
 __device__ __forceinline__ int pass1_exl(const PathArgs& a, const TileLDS& L, const TileScratch& ts,
-                                         int s, int part, lds_u16* row, uint16_t* spill,
+                                         int s, int part, lds_u16* reg, lds_u16* discard,
                                          double& fx, double& fy, double& fz) {
   const BoxUnits& k = a.bu;
   const int N = a.n_atoms;
   const int ps = L.pos(s);
   const double xs = L.X[XS_R * ps], ys = L.X[XS_R * ps + 1], zs = L.X[XS_R * ps + 2];
+  const int first = part ? EXL_ROW - 1 : 0, dir = part ? -1 : 1;
   fx = fy = fz = 0.0;
   uint32_t acc = 0;
   auto body = [&](int t, bool valid, auto record) {
@@ -1165,8 +1171,9 @@ __device__ __forceinline__ int pass1_exl(const PathArgs& a, const TileLDS& L, co
     const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
     const bool ok = valid && r2 <= k.rc2;
     if constexpr (decltype(record)::value) {
-      row[min(acc, (uint32_t)EXL_KEEP)] = (uint16_t)t;
-      if (ok && acc >= (uint32_t)EXL_KEEP) spill[acc - EXL_KEEP] = (uint16_t)t;
+      const bool keep = ok && acc < (uint32_t)EXL_ROW;
+      lds_u16* dst = keep ? reg + (first + dir * (int)acc) : discard;
+      *dst = (uint16_t)t;
       acc += ok ? 1u : 0u;
     }
     double iru = rsqrt_nr(r2);
@@ -1190,14 +1197,15 @@ __device__ __forceinline__ int pass1_exl(const PathArgs& a, const TileLDS& L, co
   return -1;
 }
 
-// Pass 2 of slot s, part `part`: q_s from the exact row (LDS entries, then
-// the spilled tail), or from the part's share of an overflow scan (ec < 0).
-// Rows are padded with the slot itself to whole chunks of 4.
+// Pass 2 of slot s, part `part`: q_s from the part's ec entries of the
+// atom's region (part 0 from the front, part 1 from the back, padded with the
+// slot itself to whole chunks of 4), from the candidate row with the cutoff
+// test when the region overflowed (ec == -2), or from the part's share of an
+// overflow scan when the candidate rows did (ec == -1).
 template <bool F32>
 __device__ __forceinline__ void pass2_exl(const PathArgs& a, const TileLDS& L, const TileScratch& ts,
-                                          int s, int part, int ec, const lds_u16* row,
-                                          const uint16_t* spill, double& qx, double& qy,
-                                          double& qz) {
+                                          int s, int part, int ec, const lds_u16* reg,
+                                          double& qx, double& qy, double& qz) {
   const BoxUnits& k = a.bu;
   const int ps = L.pos(s);
   const f64x2 o0 = lds_ld2(L.X + XS_R * ps), o1 = lds_ld2(L.X + XS_R * ps + 2),
@@ -1229,8 +1237,8 @@ __device__ __forceinline__ void pass2_exl(const PathArgs& a, const TileLDS& L, c
       qz += (double)fmaf(af, (float)wz, tt * (float)dz);
     } else {
       // padding entries name the slot itself (d = w = 0); clamping r^2 keeps
-      // their terms finite, so they add exactly 0; `ok` is false only in the
-      // overflow scan's cutoff test
+      // their terms finite, so they add exactly 0; `ok` is false only where
+      // the overflow paths below test the cutoff
       double iru = rsqrt_nr(fmax(r2, 1e-30));
       iru = ok ? iru : 0.0;
       const double ir2 = iru * iru;
@@ -1246,21 +1254,29 @@ __device__ __forceinline__ void pass2_exl(const PathArgs& a, const TileLDS& L, c
     }
   };
   if (ec >= 0) {
-    typedef __attribute__((address_space(3))) unsigned long long lds_u64;
-    const int nq = ec > EXL_KEEP ? EXL_CAP / 4 : (ec + 3) >> 2;
+    typedef __attribute__((address_space(3))) const unsigned long long lds_u64;
+    // chunk q: entries [4 q, 4 q + 4) for part 0, [EXL_ROW - 4 q - 4, EXL_ROW - 4 q) for part 1
+    lds_u64* ch = (lds_u64*)(part ? reg + (EXL_ROW - 4) : reg);
+    const int step = part ? -1 : 1;
+    const int nq = (ec + 3) >> 2;
     for (int q = 0; q < nq; ++q) {
-      const unsigned long long v = *(const lds_u64*)(row + 4 * q);  // one 8-byte LDS read
+      const unsigned long long v = ch[step * q];  // one 8-byte LDS read
       const uint2 c = make_uint2((uint32_t)v, (uint32_t)(v >> 32));
 #pragma unroll
       for (int e = 0; e < 4; ++e) body(ChunkOf<4>::entry(c, e), true);
     }
-    if (ec > EXL_KEEP) {
-      const int nq2 = (ec - EXL_KEEP + 3) >> 2;
-      for (int q = 0; q < nq2; ++q) {
-        const uint2 c = reinterpret_cast<const uint2*>(spill)[q];
-#pragma unroll
-        for (int e = 0; e < 4; ++e) body(ChunkOf<4>::entry(c, e), true);
-      }
+  } else if (ec == -2) {
+    // rare: one entry at a time, so that this path adds no registers to the
+    // common one (candidate entry j of row r is at [(j / 8) 2 N + r] 8 + j % 8)
+    const int r = 2 * s + part;
+    const size_t rows = (size_t)2 * a.n_atoms;
+    const int cnt = ts.cnt[r];
+    for (int j = 0; j < cnt; ++j) {
+      const int t = ts.nbr[((size_t)(j >> 3) * rows + r) * 8 + (j & 7)];
+      const double dx = wrap_u(xs - L.X[XS_R * t]);
+      const double dy = wrap_u(ys - L.X[XS_R * t + 1]);
+      const double dz = wrap_u(zs - L.X[XS_R * t + 2]);
+      body(t, fma(dx, dx, fma(dy, dy, dz * dz)) <= k.rc2);
     }
   } else {
     for_each_atom<false, 2>(a, L, ts, s, part, [&](int t, bool) {
@@ -1281,7 +1297,8 @@ __device__ void tile_body_exl(const PathArgs& a, int tile, const TileScratch& ts
   const int N = a.n_atoms;
   const int ncell = a.nc * a.nc * a.nc;
   TileLDS L = carve_lds(lds_base, N, ncell, true, false, false);
-  lds_u16* const EXR = L.stage;  // 2 N rows of EXL_CAP entries (shares the build's region)
+  lds_u16* const EXR = L.stage;  // N regions of EXL_ROW entries (shares the build's region)
+  lds_u16* const discard = EXR + (size_t)N * EXL_ROW + threadIdx.x;
   const int64_t n0 = (int64_t)tile * a.tile;
   const int64_t n1 = min(n0 + (int64_t)a.tile, a.n_steps);
   const size_t slice = (size_t)3 * N;
@@ -1292,7 +1309,6 @@ __device__ void tile_body_exl(const PathArgs& a, int tile, const TileScratch& ts
   const int part = lane >> 5;
   const int wv = threadIdx.x / WAVE, nwv = B / WAVE;
   const double box = a.lj.box, ib = a.lj.inv_box;
-  const int spill_stride = row_capacity<false>(a.kmax);  // entries per spilled half-row
   double hs2 = a.bu.half_skin2, rl2 = a.bu.rlist2;
 
   // Initial lists around each atom's centre over the tile (see tile_body);
@@ -1387,35 +1403,52 @@ __device__ void tile_body_exl(const PathArgs& a, int tile, const TileScratch& ts
       const int s = base + (lane & 31);
       const bool live = s < N;
       const int r = 2 * (live ? s : 0) + part;
-      lds_u16* row = EXR + (size_t)r * EXL_CAP;
-      uint16_t* spill = ts.ex + (size_t)r * spill_stride;
+      lds_u16* reg = EXR + (size_t)(live ? s : 0) * EXL_ROW;
       double f[3] = {0.0, 0.0, 0.0};
       int c = 0;
-      if (live) c = pass1_exl<GRAD>(a, L, ts, s, part, row, spill, f[0], f[1], f[2]);
+      if (live) c = pass1_exl<GRAD>(a, L, ts, s, part, reg, discard, f[0], f[1], f[2]);
 #pragma unroll
       for (int k = 0; k < 3; ++k) f[k] += __shfl_xor(f[k], 32, WAVE);
-      // even out the atom's two exact rows (both in LDS), then pad to whole chunks
+      // split the atom's partners evenly between its two lanes, then pad each
+      // part to whole chunks
       const int co = __shfl_xor(c, 32, WAVE);
       if (live && GRAD) {
-        if (c >= 0 && co >= 0 && c <= EXL_KEEP && co <= EXL_KEEP) {
-          const int E = c + co;
-          const int h = part == 0 ? (E + 1) >> 1 : E >> 1;
-          if (c > h) {
-            lds_u16* other = EXR + (size_t)(r ^ 1) * EXL_CAP;
-            for (int j = 0; j < c - h; ++j) other[co + j] = row[h + j];
-          }
-          c = h;
-        }
-        if (c >= 0) {
-          const uint16_t self = (uint16_t)L.pos(s);
-          if (c > EXL_KEEP) {
-            row[EXL_KEEP] = self;
-            for (int i = c - EXL_KEEP; i & 3; ++i) spill[i] = self;
+        int ec = -1;  // candidate rows overflowed: scan
+        if (c >= 0 && co >= 0) {
+          if (c + co > EXL_ROW) {
+            ec = -2;  // the region overflowed: candidate rows again
           } else {
-            for (int i = c; i & 3; ++i) row[i] = self;
+            const int E = c + co;
+            const int h = part == 0 ? (E + 1) >> 1 : E >> 1;
+            const int ho = E - h;
+            // This part's entries are [0, c) (part 0) or [EXL_ROW - c, EXL_ROW)
+            // (part 1); it keeps [0, h) or [EXL_ROW - h, EXL_ROW).  Surplus
+            // entries that already lie in the other part's final segment stay;
+            // the rest move to the other part's free entries next to the gap
+            // (source and destination ranges are disjoint).
+            if (c > h) {
+              int src, dst, n;
+              if (part == 0) {
+                src = h;
+                n = min(c, EXL_ROW - ho) - h;
+                dst = max(c, EXL_ROW - ho);
+              } else {
+                src = max(EXL_ROW - c, ho);
+                n = EXL_ROW - h - src;
+                dst = co;
+              }
+              for (int j = 0; j < n; ++j) reg[dst + j] = reg[src + j];
+            }
+            // the padding may overwrite surplus the other lane has just moved:
+            // both lanes are in this wave, and the barrier keeps the moves
+            // ahead of the padding in the instruction stream
+            __builtin_amdgcn_wave_barrier();
+            const uint16_t self = (uint16_t)L.pos(s);
+            for (int i = h; i & 3; ++i) reg[part == 0 ? i : EXL_ROW - 1 - i] = self;
+            ec = h;
           }
         }
-        L.ecnt[r] = (int16_t)c;
+        L.ecnt[r] = (int16_t)ec;
       }
       if (live && part == 0) {
         const int o = L.perm[s];
@@ -1461,9 +1494,8 @@ __device__ void tile_body_exl(const PathArgs& a, int tile, const TileScratch& ts
         const bool live = s < N;
         double q[3] = {0.0, 0.0, 0.0};
         if (live) {
-          const int r = 2 * s + part;
-          pass2_exl<F32>(a, L, ts, s, part, L.ecnt[r], EXR + (size_t)r * EXL_CAP,
-                         ts.ex + (size_t)r * spill_stride, q[0], q[1], q[2]);
+          pass2_exl<F32>(a, L, ts, s, part, L.ecnt[2 * s + part], EXR + (size_t)s * EXL_ROW,
+                         q[0], q[1], q[2]);
         }
 #pragma unroll
         for (int k = 0; k < 3; ++k) q[k] += __shfl_xor(q[k], 32, WAVE);

@@ -177,10 +177,12 @@ def test_lj864_em_ragged_tiles(device):
 
 @pytest.mark.parametrize("rc", [2.6, 3.2])
 def test_lj500_long_exact_rows(device, rc):
-    """Cutoffs whose exact partner rows exceed what the workgroup keeps in
-    shared memory per half-row (the tail goes to device memory), with and
-    without the two halves of an atom evened out; against the oracle and the
-    form with the exact lists in device memory (two slot arrays)."""
+    """Cutoffs at which atoms have more partners within r_c than the 64
+    shared-memory entries an atom's two lanes share (about 62 per atom on
+    average at r_c = 2.6, so some atoms overflow and most do not; about 116
+    at 3.2, so every atom does and pass 2 walks its candidate rows again with
+    the cutoff test); against the oracle and the form with the exact lists in
+    device memory (two slot arrays)."""
     import dataclasses
     from oracle import em as OE
     w = dataclasses.replace(W.workload("lj108").with_atoms(500).with_steps(12), rc=rc)
