@@ -46,6 +46,8 @@ typedef __attribute__((address_space(3))) uint16_t lds_u16;
 typedef __attribute__((address_space(3))) int16_t lds_i16;
 typedef double f64x2 __attribute__((ext_vector_type(2)));
 typedef __attribute__((address_space(3))) f64x2 lds_f64x2;
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) f32x4 lds_f32x4;
 
 // 16-byte LDS load (ds_read_b128) of two doubles at a 16-byte aligned address.
 __device__ __forceinline__ f64x2 lds_ld2(const lds_f64* p) { return *(const lds_f64x2*)p; }
@@ -257,9 +259,27 @@ __device__ __forceinline__ int row_capacity(int kmax) {
 // parked in slot element 3 for the scan (free until pass 1 stores rho).
 // Otherwise the radius^2 is rl2.  scan_radius() of the caller keeps both forms
 // conservative (a relative 1e-12 margin).
-template <int XS, bool HALF>
+//
+// With F32S (full lists, rho in LDS) the scan tests candidates in float32: a
+// float copy of each slot (position wrapped into [0, 1) box units, reach)
+// goes to the shared region after the build's scratch, and a pair is listed
+// when the float distance is within the float limit plus SCAN_MARGIN.  The
+// float rounding of the wrapped positions, of r^2 and of the limit is below
+// 1e-6 box units, so every pair the float64 test would list is listed (a few
+// more may be); the cutoff itself is tested in float64 in the passes.
+constexpr float SCAN_MARGIN = 1e-5f;  // box units
+
+__host__ __device__ inline uint32_t scan_copy_offset(int n_atoms, int ncell) {
+  return (4u * (2u * (uint32_t)ncell + 1u) + 4u * (uint32_t)n_atoms + 15u) & ~15u;
+}
+
+template <int XS, bool HALF, bool F32S = false>
 __device__ void rebuild(const PathArgs& a, const TileLDS& L, const TileScratch& ts, double rl2,
                         double rcm, const double* dsrc, double dconst) {
+  static_assert(!F32S || (XS == XS_R && !HALF), "float scan: full lists with reaches only");
+  typedef __attribute__((address_space(3))) char lds_char;
+  lds_f32x4* const C32 =
+      (lds_f32x4*)((lds_char*)L.stage + scan_copy_offset(a.n_atoms, a.nc * a.nc * a.nc));
   constexpr int PARTS = HALF ? 1 : 2;
   constexpr int SPAN = WAVE / PARTS;  // slots per wave
   const int N = a.n_atoms;
@@ -296,7 +316,16 @@ __device__ void rebuild(const PathArgs& a, const TileLDS& L, const TileScratch& 
     __syncthreads();
   }
   if constexpr (XS == XS_R) {
-    for (int s = threadIdx.x; s < N; s += B) L.X[XS * L.pos(s) + 3] = dsrc ? dsrc[L.perm[s]] : dconst;
+    for (int s = threadIdx.x; s < N; s += B) {
+      const int p = L.pos(s);
+      const double d = dsrc ? dsrc[L.perm[s]] : dconst;
+      L.X[XS * p + 3] = d;
+      if constexpr (F32S) {
+        const double x = L.X[XS * p], y = L.X[XS * p + 1], z = L.X[XS * p + 2];
+        C32[p] = f32x4{(float)(x - floor(x)), (float)(y - floor(y)), (float)(z - floor(z)),
+                       (float)d};
+      }
+    }
     __syncthreads();  // every reach parked
   }
   const int nc = a.nc, reach = a.reach;
@@ -321,6 +350,8 @@ __device__ void rebuild(const PathArgs& a, const TileLDS& L, const TileScratch& 
     const int me = L.pos(sc);
     const double xs = L.X[XS * me], ys = L.X[XS * me + 1], zs = L.X[XS * me + 2];
     const double rme = XS == XS_R ? rcm + L.X[XS * me + 3] : 0.0;  // rc + own reach
+    const float xs32 = (float)(xs - floor(xs)), ys32 = (float)(ys - floor(ys)),
+                zs32 = (float)(zs - floor(zs)), rme32 = (float)rme + SCAN_MARGIN;
     uint16_t* nb = ts.nbr;
     const uint32_t wbase = 8u * (uint32_t)(PARTS * sc + part);
     const uint32_t wcap = wbase + cap;
@@ -355,6 +386,26 @@ __device__ void rebuild(const PathArgs& a, const TileLDS& L, const TileScratch& 
       const int plast = max(p0 + np - 1, 0);  // in-range position for padded lanes
       for (int g = 0; g < nmax; g += 32) {
         uint32_t bits = 0;
+        if constexpr (F32S) {
+          for (int j = 0; j < 32; j += 2) {
+            if (g + j >= nmax) break;
+            f32x4 c[2];
+#pragma unroll
+            for (int u = 0; u < 2; ++u) c[u] = C32[min(p0 + g + j + u, plast)];
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+              const int k = g + j + u;
+              float dx = xs32 - c[u].x, dy = ys32 - c[u].y, dz = zs32 - c[u].z;
+              dx -= __builtin_rintf(dx);
+              dy -= __builtin_rintf(dy);
+              dz -= __builtin_rintf(dz);
+              const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+              const float lim = rme32 + c[u].w;
+              const bool pass = k < np && p0 + k != me && r2 <= lim * lim;
+              bits |= pass ? (1u << (j + u)) : 0u;
+            }
+          }
+        } else {
         for (int j = 0; j < 32; j += 4) {
           if (g + j >= nmax) break;
           double px[4], py[4], pz[4], pd[4];
@@ -389,6 +440,7 @@ __device__ void rebuild(const PathArgs& a, const TileLDS& L, const TileScratch& 
                               (!HALF || upper_half(dx, dy, dz, s, p0 + k));
             bits |= pass ? (1u << (j + u)) : 0u;
           }
+        }
         }
         if (!live) bits = 0;
         while (bits) {
@@ -1116,9 +1168,11 @@ size_t exl_lds_bytes(int n_atoms, int nc, int block) {
   const size_t ncell = (size_t)nc * nc * nc;
   size_t b = sizeof(double) * (size_t)n_atoms * XS_R;
   b += sizeof(double) * 32 + sizeof(int) * 18 + 6 * (size_t)n_atoms + 16;
-  // the atoms' regions, then one discard entry per thread
+  // the atoms' regions, then one discard entry per thread; during a build the
+  // same space holds the build's scratch and the float copy of the slots
   const size_t rows = ((size_t)n_atoms * EXL_ROW + (size_t)block) * sizeof(uint16_t);
-  return b + std::max<size_t>(rows, lds_shared_region(n_atoms, (int)ncell, block));
+  const size_t build = scan_copy_offset(n_atoms, (int)ncell) + 16 * (size_t)n_atoms;
+  return b + std::max({rows, build, (size_t)lds_shared_region(n_atoms, (int)ncell, block)});
 }
 
 
@@ -1384,7 +1438,7 @@ __device__ void tile_body_exl(const PathArgs& a, int tile, const TileScratch& ts
   for (int64_t n = n0; n < n1;) {
     __syncthreads();  // X holds x_n (or the centres); flag[n & 1] is final
     if (first || L.flag[n & 1]) {
-      rebuild<XS, false>(a, L, ts, rl2, rcm, first ? reach : nullptr, reach_all);
+      rebuild<XS, false, true>(a, L, ts, rl2, rcm, first ? reach : nullptr, reach_all);
       __syncthreads();  // lists and slots ready
       if (first) {
         first = false;
