@@ -470,8 +470,9 @@ int pamd_em_integrate(const pamd_path* path, const pamd_potential* pot,
                       double* x_out, void* ws, size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------------------
- * Autotuning: times candidate (block, tile, skin, list kind) choices for this
- * problem on the given inputs and caches the fastest for later calls whose
+ * Autotuning: times candidate (block, tile, skin, list kind, slot arrays)
+ * choices for this problem on the given inputs, the library's own choices
+ * among them, and caches the fastest for later calls whose
  * key matches: potential kind, n_atoms, precision, floor(log2 n_steps), and
  * for Lennard-Jones the box edge and cutoff.  Single-path calls and batch
  * members made after it (pamd_batch_create) take their launch from the cache

@@ -190,14 +190,16 @@ size_t bump(size_t& cur, size_t bytes) {
   return at;
 }
 
+// use_cache = false: fields left at 0 take the planner's own choices even
+// when the autotuner has cached others for this problem.
 int make_plan(const pamd_path* p, const pamd_potential* v, const pamd_tuning* t_in, bool mh,
-              Plan& P, int grid_cap = kMaxGrid) {
+              Plan& P, int grid_cap = kMaxGrid, bool use_cache = true) {
   int rc;
   if ((rc = check_path(p)) || (rc = check_pot(p, v)) || (rc = check_tuning(t_in))) return rc;
   pamd_tuning t{};
   if (t_in) t = *t_in;
   pamd_tuning cached{};
-  const bool have_cache = cached_tuning(p, v, &cached);
+  const bool have_cache = use_cache && cached_tuning(p, v, &cached);
   P.kind = v->kind;
   P.steps = p->n_steps;
   P.N = p->n_atoms;
@@ -1043,10 +1045,12 @@ int pamd_autotune(const pamd_path* p, const pamd_potential* v, const double* x,
                     256, 512, 1024})
         if (b >= 64 && b <= 1024 && std::find(blocks.begin(), blocks.end(), b) == blocks.end())
           blocks.push_back(b);
+      // tile 0 and skin 0 are the planner's own choices for the block, so the
+      // default launch is among the candidates
       for (int b : blocks)
         for (int slots : {2, 1}) {
-          for (int tile : {4, 8, 16, 32})
-            for (double skin : {0.2, 0.3, 0.45}) {
+          for (int tile : {0, 2, 4, 8, 16, 32})
+            for (double skin : {0.0, 0.2, 0.3, 0.45}) {
               pamd_tuning c{};
               c.algo = PAMD_ALGO_FUSED;
               c.block = b;
@@ -1069,7 +1073,7 @@ int pamd_autotune(const pamd_path* p, const pamd_potential* v, const double* x,
   bool found = false;
   for (const auto& c : cands) {
     Plan P;
-    if (make_plan(p, v, &c, false, P) != PAMD_OK) continue;
+    if (make_plan(p, v, &c, false, P, kMaxGrid, false) != PAMD_OK) continue;
     if (P.total > ws_bytes || !ws) continue;
     if (evaluate(p, v, P, x, nullptr, nullptr, nullptr, grad_scratch, nullptr, MODE_GRAD, ws, st))
       continue;
