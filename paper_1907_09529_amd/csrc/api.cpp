@@ -291,10 +291,11 @@ int make_plan(const pamd_path* p, const pamd_potential* v, const pamd_tuning* t_
     P.off_rglob = bump(cur, sizeof(double) * P.rglob_stride * P.grid);
   } else {
     const int N = P.N;
-    P.pcells = choose_cells(v->box, v->rc, N, 1 << 30);
+    P.pcells = choose_cells(v->box, v->rc, N, 1 << 30, 0.5);
     P.pkmax = t.max_neighbours > 0 ? std::min(t.max_neighbours, std::max(1, N - 1))
                                    : default_kmax(v->box, v->rc, N);
-    P.block = t.block ? t.block : 256;
+    // one thread per atom where a workgroup holds them all
+    P.block = t.block ? t.block : (int)std::min<size_t>(1024, align_up((size_t)N, 64));
     P.plds = plain_lds_bytes(N, P.pcells.nc);
     if (P.plds > kLdsMax)
       return fail(PAMD_EUNSUPPORTED, "plain form: n_atoms = %d needs %zu bytes of LDS (max %zu)", N, P.plds, kLdsMax);
@@ -444,7 +445,10 @@ int evaluate(const pamd_path* p, const pamd_potential* v, const Plan& P, const d
 
 namespace pamd {
 
-CellGrid choose_cells(double box, double radius, int n_atoms, int max_cells) {
+// cell_cost: the cost of visiting one stencil cell, in candidate tests (0
+// for the fused build, whose scan walks contiguous cell ranges; per-atom
+// stencil walks pay it per cell)
+CellGrid choose_cells(double box, double radius, int n_atoms, int max_cells, double cell_cost) {
   CellGrid g;
   const double rho = n_atoms / (box * box * box);
   double best = (double)n_atoms;  // all pairs
@@ -454,7 +458,8 @@ CellGrid choose_cells(double box, double radius, int n_atoms, int max_cells) {
     while (nc >= 2 * reach + 1 && (int64_t)nc * nc * nc > cap) --nc;
     if (nc < 2 * reach + 1) continue;
     const double h = box / nc;
-    const double cand = std::pow(2 * reach + 1, 3) * h * h * h * rho;
+    const double cells = std::pow(2 * reach + 1, 3);
+    const double cand = cells * h * h * h * rho + cell_cost * cells;
     if (cand < best) {
       best = cand;
       g.nc = nc;

@@ -154,7 +154,7 @@ struct CellGrid {
 // Cells of edge >= radius / reach for reach in 1..3, at most max_cells of
 // them (and at most 4 per atom); the variant visiting the fewest candidate
 // atoms wins.
-CellGrid choose_cells(double box, double radius, int n_atoms, int max_cells);
+CellGrid choose_cells(double box, double radius, int n_atoms, int max_cells, double cell_cost = 0.0);
 // The finest cell grid with which the fused kernel's LDS (given block size,
 // residual placement and list kind) fits kFusedLdsMax; false if none does.
 bool fused_cells_fit(double box, double radius, int n_atoms, int block, bool r_in_lds, bool half,
