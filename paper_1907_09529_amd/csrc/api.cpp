@@ -275,11 +275,10 @@ int make_plan(const pamd_path* p, const pamd_potential* v, const pamd_tuning* t_
     P.n_tiles = (int)((P.steps + P.tile - 1) / P.tile);
     P.grid = std::min(P.n_tiles, std::max(1, std::min(grid_cap, kMaxGrid)));
     P.off_bnd = bump(cur, sizeof(double) * 3 * N * (size_t)std::max(0, P.n_tiles - 1));
-    // neighbour list, then the exact list; both with one spare chunk per atom
-    // neighbour lists ((kmax + 8) per atom) and exact lists (up to two rows
-    // per atom, each with a spare chunk: kmax + 32 per atom); both get the
-    // larger size
-    P.nbr_stride = 2 * align_up((size_t)(P.kmax + 32) * N, 128);
+    // neighbour lists (two rows per atom, each with a spare chunk: kmax + 32
+    // per atom), then, unless the exact lists stay in LDS, room for exact
+    // lists of the same size
+    P.nbr_stride = (P.exl ? 1 : 2) * align_up((size_t)(P.kmax + 32) * N, 128);
     P.cnt_stride = align_up((size_t)2 * N, 64);  // list lengths: up to two rows per atom
     P.xref_stride = align_up((size_t)6 * N, 32);
     // global scratch: residuals, or with one LDS slot array the list reaches
@@ -365,6 +364,7 @@ BlockScratch scratch_of(const Plan& P, void* ws) {
   s.cnt_stride = (int64_t)P.cnt_stride;
   s.xref_stride = (int64_t)P.xref_stride;
   s.rglob_stride = (int64_t)P.rglob_stride;
+  s.ex_off = P.exl ? 0 : (int64_t)P.nbr_stride / 2;
   return s;
 }
 

@@ -320,6 +320,7 @@ int run_batch(const pamd_batch* b, const double* x_all, const double* w_all, dou
     s.xref = (double*)(base + b->off_xref);
     s.rglob = b->rglob_stride ? (double*)(base + b->off_rglob) : nullptr;
     s.nbr_stride = (int64_t)b->nbr_stride;
+    s.ex_off = (int64_t)b->nbr_stride / 2;
     s.cnt_stride = (int64_t)b->cnt_stride;
     s.xref_stride = (int64_t)b->xref_stride;
     s.rglob_stride = (int64_t)b->rglob_stride;

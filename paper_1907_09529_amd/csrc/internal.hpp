@@ -92,11 +92,12 @@ inline void set_box_units(PathArgs& a) {
 
 // Per-block scratch in global memory for the fused LJ kernel.
 struct BlockScratch {
-  uint16_t* nbr;   // per block: neighbour lists, then exact lists, (kmax + 32) * n_atoms each
+  uint16_t* nbr;   // per block: neighbour lists, then (unless ex_off is 0) exact lists, (kmax + 32) * n_atoms each
   int32_t* cnt;    // n_atoms per block
   double* xref;    // 6 * n_atoms per block: list-build positions, then rho_{n-1}
   double* rglob;   // 3 * n_atoms per block (residuals when they do not fit in LDS), or null
   int64_t nbr_stride, cnt_stride, xref_stride, rglob_stride;  // elements per block
+  int64_t ex_off;  // elements from a block's neighbour lists to its exact lists; 0: none
 };
 
 struct FusedLaunch {

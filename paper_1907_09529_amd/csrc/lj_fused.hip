@@ -1141,7 +1141,7 @@ __device__ __forceinline__ void tile_body(const PathArgs& a, int tile, const Til
 __device__ __forceinline__ TileScratch block_scratch(const BlockScratch& s) {
   TileScratch t;
   t.nbr = s.nbr + (size_t)blockIdx.x * s.nbr_stride;
-  t.ex = t.nbr + s.nbr_stride / 2;
+  t.ex = s.ex_off ? t.nbr + s.ex_off : nullptr;
   t.cnt = s.cnt + (size_t)blockIdx.x * s.cnt_stride;
   t.xref = s.xref + (size_t)blockIdx.x * s.xref_stride;
   t.rprev = t.xref + s.xref_stride / 2;

@@ -60,14 +60,18 @@ def test_noalloc_matches_workspace_call_twice_smaller_second(device):
 
 
 def test_noalloc_shrinks_the_grid_when_the_workspace_is_larger(device):
+    # the 864 x 4096 path with its exact lists in device memory (two slot
+    # arrays) plans more scratch than the static array holds
     w = W.workload("lj864")
     path, pot = lib_descriptors(w)
-    need = P.pamd_workspace_size(path, pot)
+    two = P.make_tuning("fused", slot_arrays=2)
+    need = P.pamd_workspace_size(path, pot, two)
     assert need > _lib.PAMD_NOALLOC_SCRATCH_BYTES   # the usual plan would not fit
     X = W.tethered_path(w)
-    _compare(w, X)
+    _compare(w, X, tuning=two)
+    _compare(w, X)                                  # the default launch fits as planned
     w2 = w.with_steps(256)                          # then a smaller problem again
-    _compare(w2, np.ascontiguousarray(X[:257]))
+    _compare(w2, np.ascontiguousarray(X[:257]), tuning=two)
 
 
 def test_noalloc_refuses_what_cannot_fit(device):
