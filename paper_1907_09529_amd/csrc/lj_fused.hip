@@ -260,28 +260,23 @@ __device__ __forceinline__ int row_capacity(int kmax) {
 // Otherwise the radius^2 is rl2.  scan_radius() of the caller keeps both forms
 // conservative (a relative 1e-12 margin).
 //
-// With F32S (full lists, rho in LDS) the scan tests candidates in float32: a
+// With rho in LDS and full lists the scan tests candidates in float32: a
 // float copy of each slot (position wrapped into [0, 1) box units, reach)
-// goes to the shared region after the build's scratch, and a pair is listed
-// when the float distance is within the float limit plus SCAN_MARGIN.  The
-// float rounding of the wrapped positions, of r^2 and of the limit is below
-// 1e-6 box units, so every pair the float64 test would list is listed (a few
-// more may be); the cutoff itself is tested in float64 in the passes.
+// goes to the slot's last 16 bytes, free until pass 1 stores rho, and a pair
+// is listed when the float distance is within the float limit plus
+// SCAN_MARGIN.  The float rounding of the wrapped positions, of r^2 and of the
+// limit is below 1e-6 box units, so every pair the float64 test would list is
+// listed (a few more may be); the cutoff itself is tested in float64 in the
+// passes.
 constexpr float SCAN_MARGIN = 1e-5f;  // box units
 
-__host__ __device__ inline uint32_t scan_copy_offset(int n_atoms, int ncell) {
-  return (4u * (2u * (uint32_t)ncell + 1u) + 4u * (uint32_t)n_atoms + 15u) & ~15u;
-}
-
-template <int XS, bool HALF, bool F32S = false>
+template <int XS, bool HALF>
 __device__ void rebuild(const PathArgs& a, const TileLDS& L, const TileScratch& ts, double rl2,
                         double rcm, const double* dsrc, double dconst) {
-  static_assert(!F32S || (XS == XS_R && !HALF), "float scan: full lists with reaches only");
-  typedef __attribute__((address_space(3))) char lds_char;
-  lds_f32x4* const C32 =
-      (lds_f32x4*)((lds_char*)L.stage + scan_copy_offset(a.n_atoms, a.nc * a.nc * a.nc));
   constexpr int PARTS = HALF ? 1 : 2;
   constexpr int SPAN = WAVE / PARTS;  // slots per wave
+  constexpr bool F32S = XS == XS_R && !HALF;
+  auto c32 = [&](int p) { return (lds_f32x4*)(L.X + XS * p + 4); };  // elements 4, 5 of slot p
   const int N = a.n_atoms;
   const int B = blockDim.x;
   if (a.nc > 0) {
@@ -322,8 +317,8 @@ __device__ void rebuild(const PathArgs& a, const TileLDS& L, const TileScratch& 
       L.X[XS * p + 3] = d;
       if constexpr (F32S) {
         const double x = L.X[XS * p], y = L.X[XS * p + 1], z = L.X[XS * p + 2];
-        C32[p] = f32x4{(float)(x - floor(x)), (float)(y - floor(y)), (float)(z - floor(z)),
-                       (float)d};
+        *c32(p) = f32x4{(float)(x - floor(x)), (float)(y - floor(y)), (float)(z - floor(z)),
+                        (float)d};
       }
     }
     __syncthreads();  // every reach parked
@@ -391,7 +386,7 @@ __device__ void rebuild(const PathArgs& a, const TileLDS& L, const TileScratch& 
             if (g + j >= nmax) break;
             f32x4 c[2];
 #pragma unroll
-            for (int u = 0; u < 2; ++u) c[u] = C32[min(p0 + g + j + u, plast)];
+            for (int u = 0; u < 2; ++u) c[u] = *c32(min(p0 + g + j + u, plast));
 #pragma unroll
             for (int u = 0; u < 2; ++u) {
               const int k = g + j + u;
@@ -1168,11 +1163,10 @@ size_t exl_lds_bytes(int n_atoms, int nc, int block) {
   const size_t ncell = (size_t)nc * nc * nc;
   size_t b = sizeof(double) * (size_t)n_atoms * XS_R;
   b += sizeof(double) * 32 + sizeof(int) * 18 + 6 * (size_t)n_atoms + 16;
-  // the atoms' regions, then one discard entry per thread; during a build the
-  // same space holds the build's scratch and the float copy of the slots
+  // the atoms' regions, then one discard entry per thread (the build's
+  // scratch shares the space)
   const size_t rows = ((size_t)n_atoms * EXL_ROW + (size_t)block) * sizeof(uint16_t);
-  const size_t build = scan_copy_offset(n_atoms, (int)ncell) + 16 * (size_t)n_atoms;
-  return b + std::max({rows, build, (size_t)lds_shared_region(n_atoms, (int)ncell, block)});
+  return b + std::max<size_t>(rows, lds_shared_region(n_atoms, (int)ncell, block));
 }
 
 
@@ -1438,7 +1432,7 @@ __device__ void tile_body_exl(const PathArgs& a, int tile, const TileScratch& ts
   for (int64_t n = n0; n < n1;) {
     __syncthreads();  // X holds x_n (or the centres); flag[n & 1] is final
     if (first || L.flag[n & 1]) {
-      rebuild<XS, false, true>(a, L, ts, rl2, rcm, first ? reach : nullptr, reach_all);
+      rebuild<XS, false>(a, L, ts, rl2, rcm, first ? reach : nullptr, reach_all);
       __syncthreads();  // lists and slots ready
       if (first) {
         first = false;
