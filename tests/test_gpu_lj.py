@@ -199,6 +199,33 @@ def test_lj500_long_exact_rows(device, rc):
     check(w, X, precision="fp32_force", ref=ref)
 
 
+def test_lj108_dilute_few_partners(device):
+    """A dilute gas (density 0.05, about three partners within r_c per atom,
+    many atoms with none or one) from seeded random positions at least one
+    sigma apart: the exact rows hold empty, single and odd splits between an
+    atom's two lanes; against the oracle in the default form (exact lists in
+    LDS), the two-array form and the unfused form."""
+    import dataclasses
+    from oracle import em as OE
+    w = dataclasses.replace(W.workload("lj108").with_steps(24), density=0.05)
+    rng = np.random.default_rng(1907)
+    pts = []
+    while len(pts) < w.n_atoms:                 # random sequential placement
+        p = rng.uniform(0.0, w.box, 3)
+        if all(np.sum((d := (p - q) - w.box * np.rint((p - q) / w.box)) * d) >= 1.0 for q in pts):
+            pts.append(p)
+    x0 = np.ascontiguousarray(np.array(pts).T)
+    pot = oracle_pot(w)
+    xi, eta = W.draw_noise(w)
+    X = OE.perturbed_em_path(x0, xi, eta, w.perturb_sd, pot, w.dt, w.D, w.gamma)
+    ref = oracle_full(w, X)
+    path, lpot = lib_descriptors(w)
+    assert P.pamd_launch_info(path, lpot).exact_lists == 1
+    check(w, X, ref=ref)
+    check(w, X, tuning=P.make_tuning("fused", slot_arrays=2), ref=ref)
+    check(w, X, tuning=P.make_tuning("plain"), ref=ref)
+
+
 def test_lj500_cell_list_path(device):
     # 500 atoms: n_c = 3 cells of edge >= 2.8 (reach 1) or 5 with reach 2
     w, X = em_input("lj108", n_atoms=500, n_steps=24)
