@@ -377,7 +377,7 @@ def bench_path(args, w) -> int:
     plain_run = None
     if default_run and not args.no_plain:
         # The unfused form on the same input, timed first.  Its untimed calls
-        # (about 50 ms of load) also bring the shader clock to its sustained
+        # (about 90 ms of load) also bring the shader clock to its sustained
         # level, which the first ~50 ms of load do not reach, so both legs of
         # the fused/plain ratio run at it.
         tplain = P.make_tuning("plain")
@@ -389,8 +389,8 @@ def bench_path(args, w) -> int:
             P.pamd_action_grad(path, pot, x, gp, action=actp, ws=wsp, tuning=tplain, stream=stream)
 
         n_plain = max(1, min(args.steps, 5))
-        print(f"[bench] plain form: 16 untimed and {n_plain} timed calls", file=sys.stderr, flush=True)
-        p_ms, p_kms = _time_calls(step_plain, 16, n_plain, lib, torch)
+        print(f"[bench] plain form: 30 untimed and {n_plain} timed calls", file=sys.stderr, flush=True)
+        p_ms, p_kms = _time_calls(step_plain, 30, n_plain, lib, torch)
         del wsp
         plain_run = (p_ms, gp, actp)
     print(f"[bench] warmup {args.warmup} steps, variant {args.variant}", file=sys.stderr, flush=True)
