@@ -1196,13 +1196,14 @@ __device__ __forceinline__ void for_each_listed4(const uint16_t* list, int rows,
 
 // Pass 1 of slot s, part `part`: force from candidate row 2 s + part, with
 // the partners within r_c written to the atom's region `reg` (part 0 from
-// entry 0 upwards, part 1 from entry EXL_ROW - 1 downwards; a candidate that
-// is not kept goes to the lane's discard entry).  Returns their number (which
+// entry 0 upwards, part 1 from entry EXL_ROW - 1 downwards, each entry e at
+// (e + rot) mod EXL_ROW; a candidate that is not kept goes to the lane's
+// discard entry).  Returns their number (which
 // may exceed what the region holds), or -1 after an overflow scan (then
 // nothing is recorded).
 template <bool REC>
 __device__ __forceinline__ int pass1_exl(const PathArgs& a, const TileLDS& L, const TileScratch& ts,
-                                         int s, int part, lds_u16* reg, lds_u16* discard,
+                                         int s, int part, lds_u16* reg, int rot, lds_u16* discard,
                                          double& fx, double& fy, double& fz) {
   const BoxUnits& k = a.bu;
   const int N = a.n_atoms;
@@ -1220,7 +1221,7 @@ __device__ __forceinline__ int pass1_exl(const PathArgs& a, const TileLDS& L, co
     const bool ok = valid && r2 <= k.rc2;
     if constexpr (decltype(record)::value) {
       const bool keep = ok && acc < (uint32_t)EXL_ROW;
-      lds_u16* dst = keep ? reg + (first + dir * (int)acc) : discard;
+      lds_u16* dst = keep ? reg + ((first + dir * (int)acc + rot) & (EXL_ROW - 1)) : discard;
       *dst = (uint16_t)t;
       acc += ok ? 1u : 0u;
     }
@@ -1252,7 +1253,7 @@ __device__ __forceinline__ int pass1_exl(const PathArgs& a, const TileLDS& L, co
 // overflow scan when the candidate rows did (ec == -1).
 template <bool F32>
 __device__ __forceinline__ void pass2_exl(const PathArgs& a, const TileLDS& L, const TileScratch& ts,
-                                          int s, int part, int ec, const lds_u16* reg,
+                                          int s, int part, int ec, const lds_u16* reg, int rot,
                                           double& qx, double& qy, double& qz) {
   const BoxUnits& k = a.bu;
   const int ps = L.pos(s);
@@ -1303,12 +1304,13 @@ __device__ __forceinline__ void pass2_exl(const PathArgs& a, const TileLDS& L, c
   };
   if (ec >= 0) {
     typedef __attribute__((address_space(3))) const unsigned long long lds_u64;
-    // chunk q: entries [4 q, 4 q + 4) for part 0, [EXL_ROW - 4 q - 4, EXL_ROW - 4 q) for part 1
-    lds_u64* ch = (lds_u64*)(part ? reg + (EXL_ROW - 4) : reg);
-    const int step = part ? -1 : 1;
+    // chunk q: entries [4 q, 4 q + 4) for part 0, [EXL_ROW - 4 q - 4, EXL_ROW - 4 q) for
+    // part 1, stored rotated by rot (a multiple of 4, so a chunk stays whole)
+    const lds_u64* ch = (const lds_u64*)reg;
+    const int c0 = part ? EXL_ROW / 4 - 1 : 0, step = part ? -1 : 1, r4 = rot >> 2;
     const int nq = (ec + 3) >> 2;
     for (int q = 0; q < nq; ++q) {
-      const unsigned long long v = ch[step * q];  // one 8-byte LDS read
+      const unsigned long long v = ch[(c0 + step * q + r4) & (EXL_ROW / 4 - 1)];  // 8-byte read
       const uint2 c = make_uint2((uint32_t)v, (uint32_t)(v >> 32));
 #pragma unroll
       for (int e = 0; e < 4; ++e) body(ChunkOf<4>::entry(c, e), true);
@@ -1452,9 +1454,14 @@ __device__ void tile_body_exl(const PathArgs& a, int tile, const TileScratch& ts
       const bool live = s < N;
       const int r = 2 * (live ? s : 0) + part;
       lds_u16* reg = EXR + (size_t)(live ? s : 0) * EXL_ROW;
+      // the regions of consecutive atoms lie EXL_ROW entries (128 bytes)
+      // apart, so each is rotated by 4 (s mod 16) entries: the 32 lanes of a
+      // part then reach different LDS banks
+      const int rot = 4 * (s & 15);
+      auto at = [&](int e) { return (e + rot) & (EXL_ROW - 1); };
       double f[3] = {0.0, 0.0, 0.0};
       int c = 0;
-      if (live) c = pass1_exl<GRAD>(a, L, ts, s, part, reg, discard, f[0], f[1], f[2]);
+      if (live) c = pass1_exl<GRAD>(a, L, ts, s, part, reg, rot, discard, f[0], f[1], f[2]);
 #pragma unroll
       for (int k = 0; k < 3; ++k) f[k] += __shfl_xor(f[k], 32, WAVE);
       // split the atom's partners evenly between its two lanes, then pad each
@@ -1485,14 +1492,14 @@ __device__ void tile_body_exl(const PathArgs& a, int tile, const TileScratch& ts
                 n = EXL_ROW - h - src;
                 dst = co;
               }
-              for (int j = 0; j < n; ++j) reg[dst + j] = reg[src + j];
+              for (int j = 0; j < n; ++j) reg[at(dst + j)] = reg[at(src + j)];
             }
             // the padding may overwrite surplus the other lane has just moved:
             // both lanes are in this wave, and the barrier keeps the moves
             // ahead of the padding in the instruction stream
             __builtin_amdgcn_wave_barrier();
             const uint16_t self = (uint16_t)L.pos(s);
-            for (int i = h; i & 3; ++i) reg[part == 0 ? i : EXL_ROW - 1 - i] = self;
+            for (int i = h; i & 3; ++i) reg[at(part == 0 ? i : EXL_ROW - 1 - i)] = self;
             ec = h;
           }
         }
@@ -1543,7 +1550,7 @@ __device__ void tile_body_exl(const PathArgs& a, int tile, const TileScratch& ts
         double q[3] = {0.0, 0.0, 0.0};
         if (live) {
           pass2_exl<F32>(a, L, ts, s, part, L.ecnt[2 * s + part], EXR + (size_t)s * EXL_ROW,
-                         q[0], q[1], q[2]);
+                         4 * (s & 15), q[0], q[1], q[2]);
         }
 #pragma unroll
         for (int k = 0; k < 3; ++k) q[k] += __shfl_xor(q[k], 32, WAVE);
