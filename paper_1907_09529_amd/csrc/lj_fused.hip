@@ -379,6 +379,10 @@ __device__ void rebuild(const PathArgs& a, const TileLDS& L, const TileScratch& 
         nmax = max(e1 - e0, o1 - o0);
       }
       const int plast = max(p0 + np - 1, 0);  // in-range position for padded lanes
+      // float scan: every test is computed in full (no lane branches); slot
+      // positions are 16-bit, as in the lists, which the mask tells the
+      // compiler so that the address takes a 24-bit multiply
+      auto cand = [&](int p) { return *c32((int)((uint32_t)min(p, plast) & 0xffffu)); };
       for (int g = 0; g < nmax; g += 32) {
         uint32_t bits = 0;
         if constexpr (F32S) {
@@ -386,7 +390,7 @@ __device__ void rebuild(const PathArgs& a, const TileLDS& L, const TileScratch& 
             if (g + j >= nmax) break;
             f32x4 c[2];
 #pragma unroll
-            for (int u = 0; u < 2; ++u) c[u] = *c32(min(p0 + g + j + u, plast));
+            for (int u = 0; u < 2; ++u) c[u] = cand(p0 + g + j + u);
 #pragma unroll
             for (int u = 0; u < 2; ++u) {
               const int k = g + j + u;
@@ -396,7 +400,7 @@ __device__ void rebuild(const PathArgs& a, const TileLDS& L, const TileScratch& 
               dz -= __builtin_rintf(dz);
               const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
               const float lim = rme32 + c[u].w;
-              const bool pass = k < np && p0 + k != me && r2 <= lim * lim;
+              const bool pass = (k < np) & (p0 + k != me) & (r2 <= lim * lim);
               bits |= pass ? (1u << (j + u)) : 0u;
             }
           }
