@@ -63,3 +63,30 @@ def oracle_full(w: W.Workload, X, weights=None):
     s = OA.per_step_action(X, pot, w.dt, w.D, w.gamma)
     g = OA.path_gradient(X, pot, w.dt, w.D, w.gamma, step_weights=weights)
     return s, g
+
+
+def pairs_at_the_cutoff(n_steps, period=16, alpha=0.004, rel_eps=1e-11):
+    """27 pairs of atoms, the pairs 10 sigma apart in a 30-sigma box (pairs
+    centred on a face straddle the periodic boundary); pair k moves along its
+    own random axis with separation D(n) = D* + alpha |n - n*|, where n* is
+    slice k mod period of every block of `period` slices and D* is
+    r_c (1 - rel_eps) for even k, r_c (1 + rel_eps) for odd k.  The motion is
+    collinear, so at n* the distance of the two atoms' bounding-box centres
+    over any tile holding n* minus both half-diagonals is exactly D*."""
+    import dataclasses
+    w = dataclasses.replace(W.workload("lj108").with_steps(n_steps), n_atoms=54,
+                            density=54 / 30.0 ** 3)
+    rng = np.random.default_rng(190701)
+    rc, L = w.cutoff, w.box
+    X = np.empty((n_steps + 1, 3, 54))
+    n = np.arange(n_steps + 1)
+    for k in range(27):
+        centre = (L / 3.0) * np.array([k % 3, (k // 3) % 3, k // 9])
+        u = rng.normal(size=3)
+        u /= np.linalg.norm(u)
+        d_star = rc * (1.0 - rel_eps if k % 2 == 0 else 1.0 + rel_eps)
+        n_star = (n // period) * period + k % period
+        sep = d_star + alpha * np.abs(n - n_star)
+        X[:, :, 2 * k] = centre + 0.5 * sep[:, None] * u
+        X[:, :, 2 * k + 1] = centre - 0.5 * sep[:, None] * u
+    return w, X

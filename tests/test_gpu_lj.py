@@ -20,7 +20,8 @@ import workloads as W
 from oracle import action as OA
 from oracle import sampling as OS
 
-from common import em_input, lib_descriptors, oracle_full, oracle_pot, rel, rel_inf
+from common import (em_input, lib_descriptors, oracle_full, oracle_pot, pairs_at_the_cutoff, rel,
+                    rel_inf)
 
 pytestmark = pytest.mark.gpu
 
@@ -224,6 +225,26 @@ def test_lj108_dilute_few_partners(device):
     check(w, X, ref=ref)
     check(w, X, tuning=P.make_tuning("fused", slot_arrays=2), ref=ref)
     check(w, X, tuning=P.make_tuning("plain"), ref=ref)
+
+
+def test_pairs_at_the_list_limit(device):
+    """Pairs that reach r_c (1 -/+ 1e-11) at one slice of every 16 (see
+    common.pairs_at_the_cutoff): with one-step tiles (no reach, so only the float32
+    scan's margin keeps the inner pairs), 16-step tiles aligned with the
+    closest approaches (the per-atom reach test at its limiting case), ragged
+    5-step tiles with a small skin, the two-array form and the unfused form.
+    The force-shifted pair force vanishes at r_c but its Hessian does not:
+    an inner pair dropped, or an outer one kept, moves the gradient by ~1e-5
+    of its largest entry."""
+    w, X = pairs_at_the_cutoff(48)
+    ref = oracle_full(w, X)
+    path, lpot = lib_descriptors(w)
+    assert P.pamd_launch_info(path, lpot).exact_lists == 1
+    for tuning in (None, P.make_tuning("fused", tile=1), P.make_tuning("fused", tile=16),
+                   P.make_tuning("fused", tile=5, skin=0.05),
+                   P.make_tuning("fused", tile=16, slot_arrays=2),
+                   P.make_tuning("plain")):
+        check(w, X, tuning=tuning, ref=ref)
 
 
 def test_lj500_cell_list_path(device):

@@ -148,3 +148,28 @@ def test_minimum_image_half_even():
     d = np.array([0.5, -0.5, 1.5, 2.49, -2.51]) * 2.0
     out = F.minimum_image(d, 2.0)
     assert np.allclose(out, np.array([1.0, -1.0, -1.0, 0.98, 0.98]), atol=1e-12)
+
+
+def test_cutoff_edge_pairs_decide_the_gradient():
+    """The pairs that the GPU list-limit test runs (common.pairs_at_the_cutoff,
+    closest approaches at r_c (1 -/+ 1e-11)) make the oracle's gradient
+    depend on each pair's cutoff decision far above the 1e-10 parity bound:
+    moving r_c by 2e-11 relative, which drops the inner pairs at their closest
+    approach or admits the outer ones, changes it by more than 1e-7 of its
+    largest entry.  Atoms of different pairs stay more than r_c + 1 apart, so
+    only the designed pairs interact."""
+    import dataclasses
+
+    from common import oracle_full, pairs_at_the_cutoff, rel_inf
+    w, X = pairs_at_the_cutoff(48)
+    L = w.box
+    for n in range(X.shape[0]):
+        d = X[n].T[:, None, :] - X[n].T[None, :, :]
+        d -= L * np.rint(d / L)
+        r = np.sqrt(np.sum(d * d, axis=-1))
+        other = np.arange(54)[:, None] // 2 != np.arange(54)[None, :] // 2
+        assert r[other].min() > w.cutoff + 1.0
+    _, g0 = oracle_full(w, X)
+    for f in (1.0 - 2e-11, 1.0 + 2e-11):
+        _, g1 = oracle_full(dataclasses.replace(w, rc=w.cutoff * f), X)
+        assert rel_inf(g1, g0) > 1e-7
