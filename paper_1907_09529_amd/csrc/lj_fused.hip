@@ -379,9 +379,9 @@ __device__ void rebuild(const PathArgs& a, const TileLDS& L, const TileScratch& 
         nmax = max(e1 - e0, o1 - o0);
       }
       const int plast = max(p0 + np - 1, 0);  // in-range position for padded lanes
-      // float scan: every test is computed in full (no lane branches); slot
-      // positions are 16-bit, as in the lists, which the mask tells the
-      // compiler so that the address takes a 24-bit multiply
+      // every test is computed in full (no lane branches); slot positions
+      // are 16-bit, as in the lists, which the mask tells the compiler so
+      // that the address takes a 24-bit multiply
       auto cand = [&](int p) { return *c32((int)((uint32_t)min(p, plast) & 0xffffu)); };
       for (int g = 0; g < nmax; g += 32) {
         uint32_t bits = 0;
@@ -410,7 +410,7 @@ __device__ void rebuild(const PathArgs& a, const TileLDS& L, const TileScratch& 
           double px[4], py[4], pz[4], pd[4];
 #pragma unroll
           for (int u = 0; u < 4; ++u) {
-            const int p = min(p0 + g + j + u, plast);
+            const int p = (int)((uint32_t)min(p0 + g + j + u, plast) & 0xffffu);
             if constexpr (XS == XS_R) {
               const f64x2 xy = lds_ld2(L.X + XS * p), zd = lds_ld2(L.X + XS * p + 2);
               px[u] = xy.x;
@@ -435,7 +435,7 @@ __device__ void rebuild(const PathArgs& a, const TileLDS& L, const TileScratch& 
               const double lim = rme + pd[u];
               lim2 = lim * lim;
             }
-            const bool pass = k < np && p0 + k != me && r2 <= lim2 &&
+            const bool pass = (k < np) & (p0 + k != me) & (r2 <= lim2) &
                               (!HALF || upper_half(dx, dy, dz, s, p0 + k));
             bits |= pass ? (1u << (j + u)) : 0u;
           }
