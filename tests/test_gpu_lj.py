@@ -247,6 +247,32 @@ def test_pairs_at_the_list_limit(device):
         check(w, X, tuning=tuning, ref=ref)
 
 
+def test_largest_exact_list_system(device):
+    """887 atoms, the largest system whose exact lists fit in LDS (its plan
+    uses all but 14 of the 163840 bytes; 888 atoms take the two-array form):
+    one-step, 8-step and ragged 5-step tiles against the oracle.  The start is
+    887 of the 1000 sites of a simple-cubic lattice of spacing 1.07 sigma
+    filling the box (density 0.724; r_c lies between the fifth and sixth
+    shells, so about 50 partners per atom and few overflowing rows), then a
+    seeded Euler-Maruyama path of the oracle."""
+    import dataclasses
+    from oracle import em as OE
+    w = dataclasses.replace(W.workload("lj108").with_atoms(887).with_steps(24),
+                            density=887 / 10.7 ** 3)
+    g = (np.arange(10) + 0.5) * (w.box / 10)
+    x0 = np.ascontiguousarray(np.stack(np.meshgrid(g, g, g, indexing="ij")).reshape(3, -1)[:, :887])
+    xi, eta = W.draw_noise(w)
+    X = OE.perturbed_em_path(x0, xi, eta, w.perturb_sd, oracle_pot(w), w.dt, w.D, w.gamma)
+    path, lpot = lib_descriptors(w)
+    info = P.pamd_launch_info(path, lpot)
+    assert info.exact_lists == 1 and 163840 - 64 < info.lds_bytes <= 163840
+    w888 = dataclasses.replace(w.with_atoms(888), density=888 / 10.7 ** 3)
+    assert P.pamd_launch_info(*lib_descriptors(w888)).exact_lists == 0
+    ref = oracle_full(w, X)
+    for tuning in (None, P.make_tuning("fused", tile=8), P.make_tuning("fused", tile=5)):
+        check(w, X, tuning=tuning, ref=ref)
+
+
 def test_lj500_cell_list_path(device):
     # 500 atoms: n_c = 3 cells of edge >= 2.8 (reach 1) or 5 with reach 2
     w, X = em_input("lj108", n_atoms=500, n_steps=24)
