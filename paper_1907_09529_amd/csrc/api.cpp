@@ -470,12 +470,12 @@ CellGrid choose_cells(double box, double radius, int n_atoms, int max_cells, dou
 }
 
 bool fused_cells_fit(double box, double radius, int n_atoms, int block, bool r_in_lds, bool half,
-                     CellGrid* grid, size_t* lds, bool two) {
+                     CellGrid* grid, size_t* lds, bool two, size_t cap_bytes) {
   int cap = 1 << 30;
   for (;;) {
     const CellGrid g = choose_cells(box, radius, n_atoms, cap);
     const size_t b = fused_lds_bytes(n_atoms, g.nc, r_in_lds, half, block, two);
-    if (b <= kFusedLdsMax) {
+    if (b <= cap_bytes) {
       *grid = g;
       *lds = b;
       return true;

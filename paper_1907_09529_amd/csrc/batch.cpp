@@ -172,7 +172,7 @@ int plan_batch(pamd_batch* b) {
         CellGrid g;
         size_t lds = 0;
         if (!fused_cells_fit(a.lj.box, radii[mi], a.n_atoms, L.block, r_in_lds, L.half, &g, &lds,
-                             two))
+                             two, kBatchLdsMax))
           return false;
         a.nc = g.nc;
         a.reach = g.reach;

@@ -146,6 +146,9 @@ int fused_half_slots();
 // Shared memory of the exact-lists-in-LDS kernel (n_atoms <= block).
 size_t exl_lds_bytes(int n_atoms, int nc, int block);
 constexpr size_t kFusedLdsMax = 163840;  // LDS per workgroup on gfx950
+// Dynamic LDS a batch launch may use: the batch kernel's own work-queue slot
+// takes 16 bytes of static LDS.
+constexpr size_t kBatchLdsMax = kFusedLdsMax - 16;
 
 // Cell grid of a list build: nc cells per axis (0: all pairs), stencil
 // half-width `reach` cells.
@@ -157,9 +160,9 @@ struct CellGrid {
 // atoms wins.
 CellGrid choose_cells(double box, double radius, int n_atoms, int max_cells, double cell_cost = 0.0);
 // The finest cell grid with which the fused kernel's LDS (given block size,
-// residual placement and list kind) fits kFusedLdsMax; false if none does.
+// residual placement and list kind) fits `cap` bytes; false if none does.
 bool fused_cells_fit(double box, double radius, int n_atoms, int block, bool r_in_lds, bool half,
-                     CellGrid* grid, size_t* lds, bool two = true);
+                     CellGrid* grid, size_t* lds, bool two = true, size_t cap = kFusedLdsMax);
 size_t plain_lds_bytes(int n_atoms, int nc);
 
 hipError_t launch_lj_fused(const PathArgs& a, const BlockScratch& s, const FusedLaunch& L,
