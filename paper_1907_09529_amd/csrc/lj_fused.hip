@@ -784,13 +784,14 @@ __device__ __forceinline__ void pass2_part(const PathArgs& a, const TileLDS& L, 
       }
     } else {
       // Exact-list entries need no mask: the padding entries name the slot
-      // itself (d = w = 0), and clamping r^2 away from 0 keeps every term
-      // finite, so they add exactly 0.
+      // itself (d = w = 0), and 1e-30 added to r^2 (far below one ulp of any
+      // pair's r^2, so no pair's value changes) keeps every term finite, so
+      // they add exactly 0.
       double iru;
       if constexpr (decltype(check)::value)
         iru = ok ? rsqrt_nr(r2) : 0.0;
       else
-        iru = rsqrt_nr(fmax(r2, 1e-30));
+        iru = rsqrt_nr(fma(dx, dx, fma(dy, dy, fma(dz, dz, 1e-30))));
       const double ir2 = iru * iru;
       const double ir6 = ir2 * ir2 * ir2;
       const double ir8 = ir2 * ir6;
@@ -1289,10 +1290,11 @@ __device__ __forceinline__ void pass2_exl(const PathArgs& a, const TileLDS& L, c
       qy += (double)fmaf(af, (float)wy, tt * (float)dy);
       qz += (double)fmaf(af, (float)wz, tt * (float)dz);
     } else {
-      // padding entries name the slot itself (d = w = 0); clamping r^2 keeps
-      // their terms finite, so they add exactly 0; `ok` is false only where
-      // the overflow paths below test the cutoff
-      double iru = rsqrt_nr(fmax(r2, 1e-30));
+      // padding entries name the slot itself (d = w = 0); 1e-30 added to r^2
+      // (far below one ulp of any pair's r^2) keeps their terms finite, so
+      // they add exactly 0; `ok` is false only where the overflow paths below
+      // test the cutoff
+      double iru = rsqrt_nr(fma(dx, dx, fma(dy, dy, fma(dz, dz, 1e-30))));
       iru = ok ? iru : 0.0;
       const double ir2 = iru * iru;
       const double ir6 = ir2 * ir2 * ir2;
