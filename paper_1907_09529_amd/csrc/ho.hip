@@ -4,13 +4,17 @@
 //   r_n = x_{n+1} - x_n + (dt/gamma) k x_n,   s_n = sum r_n^2 / (4 D dt),
 //   g_n = c [w_{n-1} r_{n-1} - w_n r_n (1 - (dt/gamma) k)].
 // `seg` lanes (a power of two <= 64) share a slice; per-slice sums use a
-// fixed xor-butterfly inside the segment.
+// fixed xor-butterfly inside the segment.  A path that one workgroup covers
+// in at most two rounds is done by a single workgroup (ONE), which also sums
+// the per-step terms into the action in a fixed order (each thread over its
+// slices in slice order, then the block sum), so no second launch is needed.
 #include "device.hpp"
 #include "internal.hpp"
 
 namespace pamd {
 
-__global__ void __launch_bounds__(256) ho_kernel(HOArgs a) {
+template <bool ONE>
+__global__ void __launch_bounds__(1024) ho_kernel(HOArgs a, double* action) {
   const int lane = threadIdx.x & (WAVE - 1);
   const int seg = a.seg;
   const int per_wave = WAVE / seg;
@@ -18,6 +22,7 @@ __global__ void __launch_bounds__(256) ho_kernel(HOArgs a) {
   const int64_t n_waves = ((int64_t)gridDim.x * blockDim.x) / WAVE;
   const int sub = lane / seg, sl = lane % seg;
   const double kmu = a.k * a.mu_dt;
+  double acc = 0.0;  // ONE: this thread's per-step terms, in slice order
   for (int64_t base = wave * per_wave; base <= a.n_steps; base += n_waves * per_wave) {
     const int64_t n = base + sub;
     const bool valid = n <= a.n_steps;
@@ -48,9 +53,16 @@ __global__ void __launch_bounds__(256) ho_kernel(HOArgs a) {
       e_loc += __shfl_xor(e_loc, off, WAVE);
     }
     if (valid && sl == 0 && n < a.n_steps) {
-      a.per_step[n] = s_loc * a.inv4Ddt;
+      const double v = s_loc * a.inv4Ddt;
+      a.per_step[n] = v;
+      if constexpr (ONE) acc += v;
       if (a.mode & MODE_EXCESS) a.excess[n] = e_loc * a.inv4Ddt;
     }
+  }
+  if constexpr (ONE) {
+    __shared__ double red[32];
+    const double t = block_sum(acc, red);
+    if (threadIdx.x == 0 && action) *action = t;
   }
 }
 
@@ -80,8 +92,12 @@ hipError_t launch_ho_em(const double* x0, const double* xi, double* xout, int64_
 hipError_t launch_ho(const HOArgs& a, double* action, hipStream_t st) {
   const int per_wave = WAVE / a.seg;
   const int64_t waves = (a.n_steps + 1 + per_wave - 1) / per_wave;
+  if (waves <= 32) {  // one workgroup of 16 waves, at most two rounds each
+    hipLaunchKernelGGL(ho_kernel<true>, dim3(1), dim3(1024), 0, st, a, action);
+    return hipGetLastError();
+  }
   const int64_t blocks = std::min<int64_t>((waves + 3) / 4, 8192);
-  hipLaunchKernelGGL(ho_kernel, dim3((unsigned)blocks), dim3(256), 0, st, a);
+  hipLaunchKernelGGL(ho_kernel<false>, dim3((unsigned)blocks), dim3(256), 0, st, a, nullptr);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   return launch_sum(a.per_step, a.n_steps, action, st);

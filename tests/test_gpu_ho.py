@@ -50,8 +50,13 @@ def test_ho1d_closed_form_and_weights(device):
 
 
 @pytest.mark.parametrize("n_dim,n_atoms,n_steps", [(3, 1, 17), (1, 5, 33), (3, 40, 65),
-                                                   (3, 500, 9), (1, 1, 1)])
+                                                   (3, 500, 9), (1, 1, 1), (1, 1, 2047),
+                                                   (1, 1, 2048), (3, 40, 1000)])
 def test_ho_shapes(device, n_dim, n_atoms, n_steps):
+    """Paths that one workgroup covers (up to 2047 steps of one degree of
+    freedom: the action is summed in the same launch) and larger ones (2048
+    steps, 120 degrees of freedom x 1000 steps: many workgroups and a separate
+    sum), against the oracle."""
     w = W.workload("ho1d")
     w = w.__class__(**{**w.__dict__, "n_dim": n_dim, "n_atoms": n_atoms, "n_steps": n_steps})
     xi, eta = W.draw_noise(w)
