@@ -236,10 +236,16 @@ int make_plan(const pamd_path* p, const pamd_potential* v, const pamd_tuning* t_
     // full lists with one slot per thread: the exact lists can live in LDS
     // (one slot array) when they fit; that is the default
     if (!P.half && slots != 2 && N <= P.block) {
-      const CellGrid g = choose_cells(L, radius, N, 1 << 30);
+      CellGrid g = choose_cells(L, radius, N, 1 << 30);
       const size_t b = exl_lds_bytes(N, g.nc, P.block);
       if (b <= kLdsMax) {
         P.exl = true;
+        // no cell grid and a list sphere holding most of the box: lists would
+        // keep nearly every atom, so the passes scan all atoms and no list is
+        // built (unless a list capacity or a skin is asked for)
+        if (g.nc == 0 && t.max_neighbours == 0 && t.skin == 0 &&
+            4.0 / 3.0 * M_PI * radius * radius * radius >= 0.6 * L * L * L)
+          g.reach = -1;
         P.cells = g;
         P.lds = b;
         P.r_in_lds = true;

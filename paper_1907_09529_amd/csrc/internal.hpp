@@ -60,7 +60,8 @@ struct PathArgs {
   double rlist2;          // (rc + skin)^2
   double half_skin2;      // (skin / 2)^2: rebuild when an atom moved further
   int32_t nc;             // cells per axis (0: all pairs)
-  int32_t reach;          // stencil half-width in cells
+  int32_t reach;          // stencil half-width in cells; -1 (with nc = 0, exact-list
+                          // kernel only): no lists, every pass scans all atoms
   int32_t kmax;           // list capacity per atom
   int32_t lds2;           // rho in LDS with two slot arrays (1) or one (0)
   BoxUnits bu;            // set by set_box_units() from lj, rlist2 and half_skin2

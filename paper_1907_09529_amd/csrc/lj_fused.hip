@@ -1239,7 +1239,7 @@ __device__ __forceinline__ int pass1_exl(const PathArgs& a, const TileLDS& L, co
     fy = fma(fsl, dy, fy);
     fz = fma(fsl, dz, fz);
   };
-  const int cnt = ts.cnt[2 * s + part];
+  const int cnt = a.reach < 0 ? -1 : ts.cnt[2 * s + part];  // reach -1: no lists
   if (cnt >= 0) {
     for_each_listed4(ts.nbr, 2 * N, 2 * s + part, cnt, [&](int t, bool valid) {
       body(t, valid, std::integral_constant<bool, REC>{});
@@ -1409,6 +1409,9 @@ __device__ void tile_body_exl(const PathArgs& a, int tile, const TileScratch& ts
   }
   const double reach_all = 0.5 * (sqrt(rl2) - rcm);
   bool first = true;
+  // reach -1: no lists (the list sphere would hold most of the box); both
+  // passes scan all atoms, so nothing is built and no skin is watched
+  const bool nolist = a.reach < 0;
 
   // the next slice, fetched during pass 2 (slot threadIdx.x) and stored after it
   double nx[3] = {0.0, 0.0, 0.0}, nref[3] = {0.0, 0.0, 0.0};
@@ -1423,7 +1426,7 @@ __device__ void tile_body_exl(const PathArgs& a, int tile, const TileScratch& ts
         const double du = wrap_u(u - nref[c]);
         d2 = fma(du, du, d2);
       }
-      if (!(d2 <= hs2)) L.flag[m & 1] = 1;
+      if (!nolist && !(d2 <= hs2)) L.flag[m & 1] = 1;
     }
   };
   auto fetch_next = [&](int64_t m) {
@@ -1432,7 +1435,7 @@ __device__ void tile_body_exl(const PathArgs& a, int tile, const TileScratch& ts
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         nx[c] = a.x[(size_t)m * slice + (size_t)c * N + o];
-        nref[c] = ts.xref[3 * my + c];
+        nref[c] = nolist ? 0.0 : ts.xref[3 * my + c];
       }
     }
   };
@@ -1440,8 +1443,10 @@ __device__ void tile_body_exl(const PathArgs& a, int tile, const TileScratch& ts
   for (int64_t n = n0; n < n1;) {
     __syncthreads();  // X holds x_n (or the centres); flag[n & 1] is final
     if (first || L.flag[n & 1]) {
-      rebuild<XS, false>(a, L, ts, rl2, rcm, first ? reach : nullptr, reach_all);
-      __syncthreads();  // lists and slots ready
+      if (!nolist) {
+        rebuild<XS, false>(a, L, ts, rl2, rcm, first ? reach : nullptr, reach_all);
+        __syncthreads();  // lists and slots ready
+      }
       if (first) {
         first = false;
         fetch_next(n0);
