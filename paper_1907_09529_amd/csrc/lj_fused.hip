@@ -1367,17 +1367,21 @@ __device__ void tile_body_exl(const PathArgs& a, int tile, const TileScratch& ts
   const double box = a.lj.box, ib = a.lj.inv_box;
   double hs2 = a.bu.half_skin2, rl2 = a.bu.rlist2;
 
+  // reach -1: no lists (the list sphere would hold most of the box); both
+  // passes scan all atoms, so nothing is built and no skin is watched
+  const bool nolist = a.reach < 0;
+
   // Initial lists around each atom's centre over the tile (see tile_body);
   // the per-atom reaches wait in global scratch.
   double d2max = 0.0;
   for (int i = threadIdx.x; i < N; i += B) {
     L.perm[i] = (uint16_t)i;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) ts.rprev[3 * i + c] = 0.0;
+    if (nolist) continue;
     double lo[3], hi[3];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      lo[c] = hi[c] = a.x[(size_t)n0 * slice + (size_t)c * N + i] * ib;
-      ts.rprev[3 * i + c] = 0.0;
-    }
+    for (int c = 0; c < 3; ++c) lo[c] = hi[c] = a.x[(size_t)n0 * slice + (size_t)c * N + i] * ib;
     for (int64_t m = n0 + 1; m < n1; ++m) {
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
@@ -1397,10 +1401,10 @@ __device__ void tile_body_exl(const PathArgs& a, int tile, const TileScratch& ts
     d2max = fmax(d2max, di2);
   }
   if (threadIdx.x == 0) L.flag[0] = L.flag[1] = 0;
-  d2max = block_max_all(d2max, L.red) * (1.0 + 1e-10);
+  if (!nolist) d2max = block_max_all(d2max, L.red) * (1.0 + 1e-10);
   const double rcm = sqrt(a.bu.rc2) * (1.0 + 1e-12);
   const double* reach = nullptr;
-  if (d2max <= hs2) {
+  if (!nolist && d2max <= hs2) {
     hs2 = d2max;
     const double r = sqrt(a.bu.rc2) + 2.0 * sqrt(d2max);
     rl2 = r * r * (1.0 + 1e-12);
@@ -1409,9 +1413,6 @@ __device__ void tile_body_exl(const PathArgs& a, int tile, const TileScratch& ts
   }
   const double reach_all = 0.5 * (sqrt(rl2) - rcm);
   bool first = true;
-  // reach -1: no lists (the list sphere would hold most of the box); both
-  // passes scan all atoms, so nothing is built and no skin is watched
-  const bool nolist = a.reach < 0;
 
   // the next slice, fetched during pass 2 (slot threadIdx.x) and stored after it
   double nx[3] = {0.0, 0.0, 0.0}, nref[3] = {0.0, 0.0, 0.0};
