@@ -598,8 +598,9 @@ __device__ __forceinline__ void for_each_listed(const uint16_t* list, int rows, 
   }
 }
 
-// Overflow scan (the list did not fit): atoms first, first + STEP, ... of the
-// slot's half (half lists) or of all other atoms (full lists).
+// Scan of all atoms (the list did not fit, or the path keeps no lists):
+// atoms first, first + STEP, ... of the slot's half (half lists) or of all
+// other atoms (full lists).
 template <bool HALF, int STEP, typename Pair>
 __device__ __forceinline__ void for_each_atom(const PathArgs& a, const TileLDS& L,
                                               const TileScratch& ts, int s, int first,
