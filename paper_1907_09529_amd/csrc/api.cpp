@@ -236,16 +236,10 @@ int make_plan(const pamd_path* p, const pamd_potential* v, const pamd_tuning* t_
     // full lists with one slot per thread: the exact lists can live in LDS
     // (one slot array) when they fit; that is the default
     if (!P.half && slots != 2 && N <= P.block) {
-      CellGrid g = choose_cells(L, radius, N, 1 << 30);
+      const CellGrid g = choose_cells(L, radius, N, 1 << 30);
       const size_t b = exl_lds_bytes(N, g.nc, P.block);
       if (b <= kLdsMax) {
         P.exl = true;
-        // no cell grid and a list sphere holding most of the box: lists would
-        // keep nearly every atom, so the passes scan all atoms and no list is
-        // built (unless a list capacity or a skin is asked for)
-        if (g.nc == 0 && t.max_neighbours == 0 && t.skin == 0 &&
-            4.0 / 3.0 * M_PI * radius * radius * radius >= 0.6 * L * L * L)
-          g.reach = -1;
         P.cells = g;
         P.lds = b;
         P.r_in_lds = true;
@@ -279,6 +273,14 @@ int make_plan(const pamd_path* p, const pamd_potential* v, const pamd_tuning* t_
     }
     P.tile = (int)std::min<int64_t>(tile, P.steps);
     P.n_tiles = (int)((P.steps + P.tile - 1) / P.tile);
+    // No cell grid, a list sphere holding most of the box and tiles of one or
+    // two steps: the list build would cost more than scanning all atoms in
+    // both passes (without lists a slice costs ~1.5x, the build ~1.4 slices,
+    // at 108 atoms), so the plan keeps no lists (reach -1) unless a list
+    // capacity or a skin is asked for.
+    if (P.exl && P.cells.nc == 0 && P.tile <= 2 && t.max_neighbours == 0 && t.skin == 0 &&
+        4.0 / 3.0 * M_PI * radius * radius * radius >= 0.6 * L * L * L)
+      P.cells.reach = -1;
     P.grid = std::min(P.n_tiles, std::max(1, std::min(grid_cap, kMaxGrid)));
     P.off_bnd = bump(cur, sizeof(double) * 3 * N * (size_t)std::max(0, P.n_tiles - 1));
     // neighbour lists (two rows per atom, each with a spare chunk: kmax + 32

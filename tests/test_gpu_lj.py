@@ -110,18 +110,20 @@ def test_lj108_block_sizes(device, lj108, lj108_ref, block, nlist):
 
 
 def test_lj108_without_lists(device, lj108, lj108_ref):
-    """108 atoms: the list sphere holds most of the 5.04-sigma box, so the
-    default plan builds no lists (reach -1) and both passes scan all atoms;
-    a skin given in the tuning keeps the lists.  Both against the oracle,
-    with one-step and 16-step tiles."""
+    """108 atoms: the list sphere holds most of the 5.04-sigma box, so with
+    one- and two-step tiles the plan builds no lists (reach -1) and both
+    passes scan all atoms; longer tiles or a skin given in the tuning keep
+    the lists.  All against the oracle."""
     w, X = lj108
     path, pot = lib_descriptors(w)
     assert P.pamd_launch_info(path, pot).reach == -1
+    assert P.pamd_launch_info(path, pot, P.make_tuning("fused", tile=2)).reach == -1
+    assert P.pamd_launch_info(path, pot, P.make_tuning("fused", tile=16)).reach >= 0
     assert P.pamd_launch_info(path, pot, P.make_tuning("fused", skin=0.5)).reach >= 0
-    for tuning in (None, P.make_tuning("fused", tile=16), P.make_tuning("fused", skin=0.5),
-                   P.make_tuning("fused", tile=16, skin=0.5)):
+    for tuning in (None, P.make_tuning("fused", tile=2), P.make_tuning("fused", tile=16),
+                   P.make_tuning("fused", skin=0.5)):
         check(w, X, tuning=tuning, ref=lj108_ref)
-    check(w, X, precision="fp32_force", tuning=P.make_tuning("fused", tile=16), ref=lj108_ref)
+    check(w, X, precision="fp32_force", tuning=P.make_tuning("fused", tile=2), ref=lj108_ref)
 
 
 def test_lj108_step_weights(device, lj108):

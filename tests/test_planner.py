@@ -75,18 +75,24 @@ def test_fp32_force_plans_like_fp64():
                                                              b.lds_bytes)
 
 
-def test_no_lists_only_where_the_list_sphere_holds_most_of_the_box():
+def test_no_lists_only_for_short_tiles_of_boxes_the_list_sphere_fills():
     # 108 atoms (box 5.04) and the paper's 27 atoms (box 3.78, r_c = L/2):
-    # the sphere of r_c + skin holds >= 60% of the box, so no lists (reach -1)
-    for n, dens, half in ((108, 0.8442, False), (27, 0.5, True)):
+    # the sphere of r_c + skin holds >= 60% of the box, and these paths get
+    # one-step tiles, so no lists (reach -1)
+    for n, dens, half, steps in ((108, 0.8442, False, 256), (27, 0.5, True, 4096)):
         box = (n / dens) ** (1.0 / 3.0)
-        path = P.make_path(4096, n, 3, 1e-4, 1.0, 1.0)
+        path = P.make_path(steps, n, 3, 1e-4, 1.0, 1.0)
         pot = P.make_potential("lj", rc=0.5 * box if half else 2.5, box=box)
         info = P.pamd_launch_info(path, pot)
-        assert info.exact_lists == 1 and info.cells == 0 and info.reach == -1
-        # a skin or a list capacity asked for keeps the lists
-        for t in (P.make_tuning("fused", skin=0.3), P.make_tuning("fused", max_neighbours=64)):
+        assert info.exact_lists == 1 and info.cells == 0 and info.tile == 1 and info.reach == -1
+        assert P.pamd_launch_info(path, pot, P.make_tuning("fused", tile=2)).reach == -1
+        # longer tiles amortise a list build; a skin or a list capacity asked
+        # for keeps the lists
+        for t in (P.make_tuning("fused", tile=3), P.make_tuning("fused", skin=0.3),
+                  P.make_tuning("fused", max_neighbours=64)):
             assert P.pamd_launch_info(path, pot, t).reach == 0
+        long_path = P.make_path(100000, n, 3, 1e-4, 1.0, 1.0)
+        assert P.pamd_launch_info(long_path, pot).reach == 0
     # 256 atoms (box 6.72): no cell grid, but the sphere holds 37% of the box
     path, pot = lj(256, 256)
     info = P.pamd_launch_info(path, pot)
