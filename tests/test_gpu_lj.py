@@ -182,6 +182,37 @@ def test_single_step_and_short_paths(device):
         check(w, X, tuning=P.make_tuning("plain"))
 
 
+@pytest.mark.parametrize("n_atoms,box", [(1, 6.0), (2, 6.0), (3, 6.0), (3, 4.0)])
+def test_tiny_systems(device, n_atoms, box):
+    """One to three atoms: no pair at all (one atom: the action is the free
+    Brownian one, sum |x_{n+1} - x_n|^2 / (4 D dt)), a single pair, and three
+    atoms with lists (6-sigma box, r_c 2.5) and without (4-sigma box, r_c = L/2:
+    the list sphere fills the box).  Seeded positions at least 1.1 sigma apart,
+    then a seeded Euler-Maruyama path of the oracle; fused and unfused forms."""
+    import dataclasses
+    from oracle import em as OE
+    w = dataclasses.replace(W.workload("lj108").with_steps(20), n_atoms=n_atoms,
+                            density=n_atoms / box ** 3, rc=2.5 if box > 5.0 else 0.0)
+    rng = np.random.default_rng(1900 + 10 * n_atoms + int(box))
+    pts = []
+    while len(pts) < n_atoms:
+        p = rng.uniform(0.0, w.box, 3)
+        if all(np.linalg.norm((p - q) - w.box * np.rint((p - q) / w.box)) >= 1.1 for q in pts):
+            pts.append(p)
+    x0 = np.ascontiguousarray(np.array(pts).T)
+    xi, eta = W.draw_noise(w)
+    X = OE.perturbed_em_path(x0, xi, eta, w.perturb_sd, oracle_pot(w), w.dt, w.D, w.gamma)
+    ref = oracle_full(w, X)
+    if box < 5.0:
+        assert P.pamd_launch_info(*lib_descriptors(w)).reach == -1
+    check(w, X, ref=ref)
+    check(w, X, tuning=P.make_tuning("plain"), ref=ref)
+    if n_atoms == 1:
+        S, _, _ = run(w, X)
+        free = math.fsum((np.diff(X, axis=0) ** 2).ravel().tolist()) / (4 * w.D * w.dt)
+        assert rel(S, free) <= ACTION_TOL
+
+
 def test_lj864_em_ragged_tiles(device):
     w, X = em_input("lj864", n_steps=40)
     ref = oracle_full(w, X)
